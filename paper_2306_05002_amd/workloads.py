@@ -1,0 +1,208 @@
+"""Seeded synthetic workloads: mesh descriptions, parameters and primitive
+initial fields of the five benchmark configurations.
+
+This module is the only code shared by the HIP path and the test oracle.  It
+holds none of the method's arithmetic: it evaluates analytic initial
+conditions (signed distances, logistic profiles, a smeared planar shock from
+the textbook Rankine-Hugoniot relations, a hydrostatic column) at node
+coordinates that the caller supplies, and returns *primitive* fields
+(alpha, psi, phase densities, velocity, pressure).  Each side turns them
+into conserved state with its own stiffened-gas map.  Everything is numpy
+float64 and deterministic (fixed seeds).
+
+Configurations (all p = 3, i.e. four GLL nodes per direction):
+  drop1d     1D periodic air/water slab on [0,1], 100 elements, u = 1, P = 1
+  drop2d     2D periodic water droplet (R 0.15) in air, 128 x 128, u = (1, 0.5)
+  shock2d    2D shock (pressure ratio 10 in air) onto a water cylinder,
+             512 x 256 on [0,2] x [0,1]; Dirichlet inflow, outflow, periodic y
+  rt3d       3D heavy-over-light box, 96^3, gravity, viscosity, surface tension,
+             slip walls in z
+  adjoint2d  drop2d plus viscosity 1e-3 and surface tension 1e-2
+Phase 1 is air (gamma 1.4, P_inf 0), phase 2 water-like (gamma 4.4,
+P_inf 0.6); alpha is the volume fraction of phase 1 and psi increases
+towards phase 1, alpha = 1 / (1 + exp(-psi / eps)).
+"""
+
+import math
+
+import numpy as np
+
+ORDER = 3
+NAMES = ("drop1d", "drop2d", "shock2d", "rt3d", "adjoint2d")
+FULL_ELEMS = {
+    "drop1d": (100,),
+    "drop2d": (128, 128),
+    "shock2d": (512, 256),
+    "rt3d": (96, 96, 96),
+    "adjoint2d": (128, 128),
+}
+
+
+def _sigmoid(z):
+    out = np.empty_like(z)
+    pos = z >= 0
+    out[pos] = 1.0 / (1.0 + np.exp(-z[pos]))
+    ez = np.exp(z[~pos])
+    out[~pos] = ez / (1.0 + ez)
+    return out
+
+
+def _softplus(z):
+    return np.maximum(z, 0.0) + np.log1p(np.exp(-np.abs(z)))
+
+
+def shock_states(pressure_ratio=10.0, gamma=1.4, rho_pre=1.0, p_pre=1.0):
+    """Post-shock density and velocity of a normal shock moving into gas at
+    rest (textbook Rankine-Hugoniot relations for a calorically perfect gas)."""
+    pi_ = pressure_ratio
+    rho_ratio = ((gamma + 1) * pi_ + (gamma - 1)) / ((gamma - 1) * pi_ + (gamma + 1))
+    ms = math.sqrt(1.0 + (gamma + 1) * (pi_ - 1) / (2 * gamma))
+    w = ms * math.sqrt(gamma * p_pre / rho_pre)
+    rho_post = rho_pre * rho_ratio
+    u_post = w * (1.0 - rho_pre / rho_post)
+    return rho_post, u_post, p_pre * pi_
+
+
+def config(name, n_elem=None):
+    """Mesh description and physical parameters of a configuration.
+
+    ``n_elem`` overrides the element counts (reduced sizes for parity tests);
+    eps follows the rule eps = h / (2 (p+1)) of the configuration's own grid.
+    """
+    if name not in NAMES:
+        raise KeyError(name)
+    n_elem = tuple(n_elem) if n_elem is not None else FULL_ELEMS[name]
+    p = ORDER
+    base = dict(gamma=(1.4, 4.4), pinf=(0.0, 0.6), rho0=(1.0, 10.0), Gamma=1.0,
+                mu=(0.0, 0.0), sigma=0.0, g=(0.0, 0.0, 0.0), c_ip=1.0,
+                grad_reg=1e-12)
+    cfg = dict(name=name, order=p, n_elem=n_elem, cfl=0.1, freeze_dt=False)
+    if name == "drop1d":
+        cfg.update(dim=1, lo=(0.0,), hi=(1.0,), bc=[("periodic", "periodic")],
+                   steps=4200)
+    elif name in ("drop2d", "adjoint2d"):
+        cfg.update(dim=2, lo=(0.0, 0.0), hi=(1.0, 1.0),
+                   bc=[("periodic", "periodic")] * 2, steps=20)
+        if name == "adjoint2d":
+            base.update(mu=(1e-3, 1e-3), sigma=1e-2)
+            cfg.update(steps=400, freeze_dt=True, checkpoint_every=20)
+    elif name == "shock2d":
+        cfg.update(dim=2, lo=(0.0, 0.0), hi=(2.0, 1.0),
+                   bc=[("dirichlet", "extrapolate"), ("periodic", "periodic")],
+                   steps=200)
+        rho_post, u_post, p_post = shock_states()
+        cfg["bc_prim"] = {(0, 0): dict(alpha=1.0, psi=0.0, rho1=rho_post,
+                                       rho2=base["rho0"][1], u=(u_post, 0.0),
+                                       P=p_post)}
+    elif name == "rt3d":
+        cfg.update(dim=3, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
+                   bc=[("periodic", "periodic")] * 2 + [("slip_wall", "slip_wall")],
+                   steps=100)
+        base.update(rho0=(1.0, 3.0), mu=(1e-3, 1e-3), sigma=1e-3, g=(0.0, 0.0, -1.0))
+    d = cfg["dim"]
+    if len(n_elem) != d:
+        raise ValueError("n_elem has the wrong length")
+    h = min((cfg["hi"][k] - cfg["lo"][k]) / n_elem[k] for k in range(d))
+    base["eps"] = 0.5 * h / (p + 1)
+    cfg["params"] = base
+    cfg.setdefault("bc_prim", {})
+    return cfg
+
+
+def _rt_interface_noise(x, y):
+    """Seeded 1e-3 perturbation of the Rayleigh-Taylor interface: 4 x 4 Fourier
+    modes with N(0,1) amplitudes (seed 3), scaled to max |zeta| = 1 on a 256^2
+    grid."""
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((4, 4))
+    B = rng.standard_normal((4, 4))
+
+    def zeta(xx, yy):
+        z = np.zeros_like(xx)
+        for m in range(1, 5):
+            for n in range(1, 5):
+                arg = 2.0 * math.pi * (m * xx + n * yy)
+                z += A[m - 1, n - 1] * np.cos(arg) + B[m - 1, n - 1] * np.sin(arg)
+        return z
+
+    g = (np.arange(256) + 0.5) / 256.0
+    gx, gy = np.meshgrid(g, g, indexing="ij")
+    scale = np.abs(zeta(gx, gy)).max()
+    return zeta(x, y) / scale
+
+
+def primitive_fields(cfg, coords, variant=None):
+    """Primitive initial fields at the given node coordinates.
+
+    coords: float64 array of shape (d, ...) (usually (d, E, nn)).
+    Returns dict(alpha, psi, rho1, rho2, P, u) with u of shape (d, ...).
+    ``variant="noisy_u"`` (drop1d only) adds 1e-3 N(0,1) noise per node to u
+    (seed 0).
+    """
+    name = cfg["name"]
+    d = cfg["dim"]
+    prm = cfg["params"]
+    eps = prm["eps"]
+    X = np.asarray(coords, dtype=np.float64)
+    shp = X.shape[1:]
+    r1, r2 = prm["rho0"]
+    rho1 = np.full(shp, r1)
+    rho2 = np.full(shp, r2)
+    u = np.zeros((d,) + shp)
+    P = np.ones(shp)
+    if name == "drop1d":
+        psi = np.abs(X[0] - 0.5) - 0.25
+        u[0] = 1.0
+        if variant == "noisy_u":
+            rng = np.random.default_rng(0)
+            u[0] = 1.0 + 1e-3 * rng.standard_normal(shp)
+    elif name in ("drop2d", "adjoint2d"):
+        psi = np.sqrt((X[0] - 0.5) ** 2 + (X[1] - 0.5) ** 2) - 0.15
+        u[0] = 1.0
+        u[1] = 0.5
+    elif name == "shock2d":
+        psi = np.sqrt((X[0] - 0.5) ** 2 + (X[1] - 0.5) ** 2) - 0.1
+        h = (cfg["hi"][0] - cfg["lo"][0]) / cfg["n_elem"][0]
+        w = _sigmoid(-(X[0] - 0.38) / (0.5 * h))
+        rho_post, u_post, p_post = shock_states()
+        rho1 = w * rho_post + (1.0 - w) * 1.0
+        u[0] = w * u_post
+        P = w * p_post + (1.0 - w) * 1.0
+    elif name == "rt3d":
+        x, y, z = X[0], X[1], X[2]
+        eta = (0.5 + 0.02 * np.cos(2 * math.pi * x) * np.cos(2 * math.pi * y)
+               + 1e-3 * _rt_interface_noise(x, y))
+        psi = eta - z
+        # hydrostatic column for g = -e_z, P(z=1) = 1:
+        # P = 1 + int_z^1 rho dz' with rho = rho2 + (rho1 - rho2) alpha
+        P = (1.0 + r2 * (1.0 - z)
+             + (r1 - r2) * eps * (_softplus((eta - z) / eps) - _softplus((eta - 1.0) / eps)))
+    else:
+        raise KeyError(name)
+    alpha = _sigmoid(psi / eps)
+    return dict(alpha=alpha, psi=psi, rho1=rho1, rho2=rho2, P=P, u=u)
+
+
+def adjoint_target_perturbation(coords):
+    """Smooth seeded perturbation (2 Fourier modes per velocity component,
+    amplitudes N(0,1) with seed 4) used to build the adjoint target run."""
+    X = np.asarray(coords, dtype=np.float64)
+    d = X.shape[0]
+    rng = np.random.default_rng(4)
+    amp = rng.standard_normal((d, 2, 2))
+    out = np.zeros_like(X)
+    for j in range(d):
+        for m in range(2):
+            arg = 2.0 * math.pi * (m + 1) * (X[0] + (m + 1) * X[d - 1])
+            out[j] += amp[j, m, 0] * np.cos(arg) + amp[j, m, 1] * np.sin(arg)
+    return out
+
+
+def fd_direction(shape_u, k):
+    """Seeded finite-difference direction k: nodal N(0,1) velocity components
+    and one N(0,1) surface-tension component (seed 1000 + k), not yet
+    normalised."""
+    rng = np.random.default_rng(1000 + k)
+    du = rng.standard_normal(shape_u)
+    ds = float(rng.standard_normal())
+    return du, ds
