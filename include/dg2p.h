@@ -1,0 +1,187 @@
+/*
+ * dg2p -- explicit DG residual of the quasi-conservative five-equation
+ * two-phase model with Allen-Cahn interface terms, on one MI355X (gfx950).
+ *
+ * Method: Tonicello & Ihme, "A high-order diffused-interface approach for
+ * two-phase compressible flow simulations using a Discontinuous Galerkin
+ * framework" (arXiv 2306.05002).  The system solved is the one of Section
+ * "Five equation model" (phase field phi_1 = alpha with the Allen-Cahn flux
+ * a_1 = Gamma (eps grad alpha - alpha (1 - alpha) n), n = grad psi/|grad psi|
+ * from the extra level set psi; partial densities with R_l = rho_l^(0) a_l;
+ * momentum and energy with f = sum_l R_l, viscous stress, CSF surface
+ * tension and gravity; stiffened-gas closure with the mixture rules), in the
+ * DG form of Section "Discontinuous Galerkin discretisation": nodal GLL
+ * collocation, Lax-Friedrichs fluxes for the convective terms, symmetric
+ * interior penalty for every a_l-built flux, and the hat/tilde face fluxes
+ * of the quasi-conservative transport of alpha and psi.
+ *
+ * Layouts (all arrays FP64 unless stated):
+ *   element index  e = e_x + N_x (e_y + N_y e_z)   (x fastest)
+ *   node index     j = a_x + 4 (a_y + 4 a_z)       (p = 3: 4 GLL nodes per axis)
+ *   state          U[f][e][j], f = 0: alpha_1 rho_1, 1: alpha_2 rho_2,
+ *                  2..d+1: rho u, d+2: rho E, d+3: alpha, d+4: psi
+ *                  (N_f = d + 5 fields)
+ *   primitives     P[f][e][j], f = 0: alpha, 1: psi, 2: rho_1, 3: rho_2,
+ *                  4..d+3: u, d+4: pressure
+ *
+ * Conventions
+ *   - Pointers marked "device" are device memory owned by the caller; the
+ *     library keeps no pointer beyond a call.  Pointers marked "host" are
+ *     host memory.  `stream` is a hipStream_t passed as void* (NULL = the
+ *     default stream); every device call is stream-ordered and asynchronous.
+ *   - The library allocates no device memory: every call that needs scratch
+ *     space takes a caller-owned workspace of dg2p_workspace_size() bytes,
+ *     256-byte aligned.  A mesh and a workspace must not be used by two
+ *     overlapping calls.
+ *   - Every function returns a dg2p_status.  Argument errors are reported
+ *     synchronously and nothing is launched; dg2p_last_error() gives the
+ *     detail (thread-local).  Non-physical states are never fatal inside a
+ *     call: they are counted in dg2p_monitors.nonphys.
+ *   - Only polynomial order p = 3 is implemented (DG2P_EUNSUPPORTED else).
+ */
+#ifndef DG2P_H
+#define DG2P_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dg2p_mesh_s* dg2p_mesh; /* opaque, owned by the library */
+
+typedef enum {
+  DG2P_OK = 0,
+  DG2P_EINVAL = -1,       /* bad argument (null pointer, size, enum value) */
+  DG2P_EHIP = -2,         /* a HIP runtime call failed (launch, copy) */
+  DG2P_ENONPHYS = -3,     /* reserved for callers: non-physical state seen */
+  DG2P_EUNSUPPORTED = -4, /* valid request the library does not implement */
+  DG2P_EWORKSPACE = -5    /* workspace missing or misaligned */
+} dg2p_status;
+
+typedef enum {
+  DG2P_BC_PERIODIC = 0,   /* wrap to the opposite side (both sides of an axis) */
+  DG2P_BC_SLIP_WALL = 1,  /* mirror: normal momentum and normal gradients negated */
+  DG2P_BC_DIRICHLET = 2,  /* prescribed (q1, q2, rho u, rho E, alpha); interior psi
+                             and gradients */
+  DG2P_BC_EXTRAPOLATE = 3 /* ghost = interior (state and gradients) */
+} dg2p_bc;
+
+typedef enum {
+  DG2P_FP64 = 0,       /* every operation in FP64 */
+  DG2P_MIXED_FP32 = 1, /* derivative and lift contractions in FP32 with FP32
+                          accumulation; closure, mixture sums, fluxes and the
+                          RK accumulation in FP64 */
+  DG2P_MIXED_BF16 = 2  /* as FP32 but contraction inputs rounded to BF16 */
+} dg2p_precision;
+
+typedef enum {
+  DG2P_OP_RHS = 0,
+  DG2P_OP_RK_STEP = 1,
+  DG2P_OP_MAX_DT = 2,
+  DG2P_OP_MONITORS = 3,
+  DG2P_OP_RHS_VJP = 4,
+  DG2P_OP_RK_STEP_VJP = 5
+} dg2p_op;
+
+/* Structured Cartesian grid of dim-dimensional tensor-product elements
+ * (the partition of the domain into elements, Section "Discontinuous
+ * Galerkin discretisation").  Entries beyond `dim` are ignored. */
+typedef struct {
+  int dim;                   /* 1, 2 or 3 */
+  int order;                 /* polynomial degree p (must be 3) */
+  int n_elem[3];             /* elements per axis, >= 1 */
+  double lo[3], hi[3];       /* box corners, hi > lo */
+  int bc[3][2];              /* dg2p_bc per axis and side (0 = low, 1 = high) */
+  double bc_state[3][2][8];  /* Dirichlet conserved state per side (first d+4
+                                entries used: q1, q2, rho u, rho E, alpha) */
+} dg2p_mesh_desc;
+
+/* Physical and numerical parameters (Section "Five equation model"). */
+typedef struct {
+  double gamma[2], pinf[2];  /* stiffened-gas gamma_l > 1, P_inf_l */
+  double rho0[2];            /* reference densities rho_l^(0) of R_l = rho_l^(0) a_l */
+  double Gamma, eps;         /* Allen-Cahn velocity scale and thickness */
+  double mu[2];              /* phase viscosities; both 0 disables viscous terms */
+  double sigma;              /* surface tension; 0 disables CSF */
+  double g[3];               /* gravity */
+  double c_ip;               /* interior-penalty constant (eta = c_ip nu (p+1)^2/h) */
+  double grad_reg;           /* delta of n = g/sqrt(g.g + delta^2) (e.g. 1e-12) */
+  int precision;             /* dg2p_precision */
+} dg2p_params;
+
+/* Step monitors (device struct written by dg2p_compute_monitors / dg2p_max_dt). */
+typedef struct {
+  double max_rate;     /* max_nodes(sum|u_k| + d c)/h_min + (p+1)^2 d nu_max/h_min^2 */
+  double dt;           /* cfl / max_rate (written by dg2p_max_dt) */
+  double min_alpha, max_alpha;
+  double integral[8];  /* sum_j W_j U[f][e][j] per field (diagonal GLL mass) */
+  double dev_p, dev_u; /* max |P - p_ref|, max_k |u_k - u_ref_k| */
+  long long nonphys;   /* nodes with rho <= 0, xi rho <= 0, (1+xi)P + Pi <= 0 or non-finite */
+} dg2p_monitors;
+
+/* Version string of the library. */
+const char* dg2p_version(void);
+
+/* Human-readable name of a status code. */
+const char* dg2p_status_string(int status);
+
+/* Detail of the last error of the calling thread ("" if none). */
+const char* dg2p_last_error(void);
+
+/* Create a mesh handle from a host descriptor.  Validates the descriptor
+ * (EINVAL), rejects p != 3 (EUNSUPPORTED).  Host only, allocates no device
+ * memory.  *out is owned by the caller until dg2p_destroy_mesh. */
+int dg2p_create_mesh(const dg2p_mesh_desc* desc /*host*/, dg2p_mesh* out /*host*/);
+
+/* Release a mesh handle (NULL is accepted). */
+int dg2p_destroy_mesh(dg2p_mesh m);
+
+/* Field count N_f = d + 5, element count E and nodes per element 4^d (host outputs). */
+int dg2p_layout(dg2p_mesh m, int* n_fields, long long* n_elem, int* nodes_per_elem);
+
+/* Physical GLL node coordinates, host array xyz[d][E][4^d] (caller-owned). */
+int dg2p_node_coords(dg2p_mesh m, double* xyz /*host*/);
+
+/* Bytes of device workspace that `op` needs for this mesh and parameters. */
+int dg2p_workspace_size(dg2p_mesh m, const dg2p_params* p /*host*/, int op, size_t* bytes /*host*/);
+
+/* Initial-condition map (the stiffened-gas law solved for rho e):
+ * U = (alpha rho_1, (1-alpha) rho_2, rho u, xi P + Pi + rho |u|^2/2, alpha, psi).
+ * prim, U: device arrays [N_f][E][4^d] (layouts above); may not alias. */
+int dg2p_prim_to_cons(dg2p_mesh m, const dg2p_params* p /*host*/, const double* prim /*device*/,
+                      double* U /*device*/, void* stream);
+
+/* Semi-discrete residual R = dU/dt (mass matrix already inverted): volume
+ * terms in strong form (equal to the paper's weak form under GLL
+ * collocation), Lax-Friedrichs / SIPG / hat-tilde face terms, IIPG viscous
+ * stresses, CSF and gravity sources.  U, R: device [N_f][E][4^d], no alias.
+ * work: device, dg2p_workspace_size(DG2P_OP_RHS) bytes. */
+int dg2p_rhs(dg2p_mesh m, const dg2p_params* p /*host*/, const double* U /*device*/,
+             double* R /*device*/, void* work /*device*/, void* stream);
+
+/* Time step dt = cfl / max_rate (rule above, recomputed from U) written to
+ * the device scalar *dt; if mon != NULL also mon->max_rate and mon->dt.
+ * work: dg2p_workspace_size(DG2P_OP_MAX_DT) bytes. */
+int dg2p_max_dt(dg2p_mesh m, const dg2p_params* p /*host*/, const double* U /*device*/,
+                double cfl, double* dt /*device*/, dg2p_monitors* mon /*device, nullable*/,
+                void* work /*device*/, void* stream);
+
+/* One Shu-Osher SSP-RK3 step in place, FP64 stage accumulation:
+ * U1 = U + dt R(U); U2 = 3/4 U + 1/4 (U1 + dt R(U1)); U <- 1/3 U + 2/3 (U2 + dt R(U2)).
+ * dt: device scalar (no host synchronisation).  work: DG2P_OP_RK_STEP bytes. */
+int dg2p_rk_step(dg2p_mesh m, const dg2p_params* p /*host*/, double* U /*device, in/out*/,
+                 const double* dt /*device*/, void* work /*device*/, void* stream);
+
+/* Monitors of a state (all fields of *mon; dt is set to 0.1 / max_rate).  p_ref and u_ref are
+ * the reference pressure and velocity of dev_p / dev_u (host values).
+ * work: DG2P_OP_MONITORS bytes.  Deterministic (fixed reduction order). */
+int dg2p_compute_monitors(dg2p_mesh m, const dg2p_params* p /*host*/, const double* U /*device*/,
+                  double p_ref, const double* u_ref /*host, d values*/,
+                  dg2p_monitors* mon /*device*/, void* work /*device*/, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DG2P_H */

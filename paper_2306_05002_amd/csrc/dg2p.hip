@@ -1,0 +1,450 @@
+// Host side of libdg2p: the C ABI declared in include/dg2p.h.
+//
+// Validation, workspace carving and launch orchestration.  All device work
+// is stream-ordered; nothing here synchronises the device or allocates
+// device memory.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/dg2p.h"
+#include "dg2p_device.hpp"
+
+using namespace dg2p;
+
+struct dg2p_mesh_s {
+  dg2p_mesh_desc desc;
+  int dim;
+  int N[3];
+  long long E;
+  int nn, nf, nfn;
+  double h[3], J[3];
+  double xi[4], w[4], D[4][4];
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return DG2P_OK;
+  return fail(DG2P_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// GLL nodes and weights of degree 3 in closed form, and the Lagrange
+// derivative matrix D[a][b] = l_b'(xi_a) from the product rule.
+void gll3(double* x, double* w, double (*D)[4]) {
+  const double s = 1.0 / std::sqrt(5.0);
+  x[0] = -1.0;
+  x[1] = -s;
+  x[2] = s;
+  x[3] = 1.0;
+  w[0] = w[3] = 1.0 / 6.0;
+  w[1] = w[2] = 5.0 / 6.0;
+  for (int a = 0; a < 4; ++a) {
+    for (int b = 0; b < 4; ++b) {
+      if (a == b) {
+        double t = 0.0;
+        for (int m = 0; m < 4; ++m)
+          if (m != a) t += 1.0 / (x[a] - x[m]);
+        D[a][b] = t;
+      } else {
+        double num = 1.0, den = 1.0;
+        for (int m = 0; m < 4; ++m) {
+          if (m != b) den *= (x[b] - x[m]);
+          if (m != a && m != b) num *= (x[a] - x[m]);
+        }
+        D[a][b] = num / den;
+      }
+    }
+  }
+}
+
+int check_params(const dg2p_mesh_s* m, const dg2p_params* p) {
+  if (!p) return fail(DG2P_EINVAL, "params is NULL");
+  for (int l = 0; l < 2; ++l) {
+    if (!(p->gamma[l] > 1.0)) return fail(DG2P_EINVAL, "gamma must be > 1");
+    if (!std::isfinite(p->pinf[l]) || !std::isfinite(p->rho0[l]))
+      return fail(DG2P_EINVAL, "pinf / rho0 must be finite");
+    if (!(p->mu[l] >= 0.0)) return fail(DG2P_EINVAL, "mu must be >= 0");
+  }
+  if (!(p->Gamma >= 0.0) || !(p->eps > 0.0)) return fail(DG2P_EINVAL, "Gamma >= 0 and eps > 0 required");
+  if (!(p->c_ip > 0.0)) return fail(DG2P_EINVAL, "c_ip must be > 0");
+  if (!(p->grad_reg >= 0.0)) return fail(DG2P_EINVAL, "grad_reg must be >= 0");
+  if (!std::isfinite(p->sigma)) return fail(DG2P_EINVAL, "sigma must be finite");
+  if (p->precision != DG2P_FP64)
+    return fail(DG2P_EUNSUPPORTED, "only DG2P_FP64 is available in this build");
+  (void)m;
+  return DG2P_OK;
+}
+
+bool viscous(const dg2p_params* p) { return p->mu[0] != 0.0 || p->mu[1] != 0.0; }
+
+KArgs make_args(const dg2p_mesh_s* m, const dg2p_params* p) {
+  KArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.E = m->E;
+  for (int k = 0; k < 3; ++k) {
+    A.N[k] = k < m->dim ? m->N[k] : 1;
+    for (int s = 0; s < 2; ++s) {
+      A.bc[k][s] = k < m->dim ? m->desc.bc[k][s] : DG2P_BC_PERIODIC;
+      for (int f = 0; f < 8; ++f) A.bcs[k][s][f] = m->desc.bc_state[k][s][f];
+    }
+    const double J = k < m->dim ? m->J[k] : 1.0;
+    const double h = k < m->dim ? m->h[k] : 1.0;
+    A.Jinv[k] = 1.0 / J;
+    A.lift[k] = 1.0 / (m->w[0] * J);
+    A.pen[k] = p->c_ip * 16.0 / h;
+    for (int a = 0; a < 4; ++a) {
+      A.symw[k][0][a] = m->D[0][a] / (2.0 * m->w[a] * J * J);
+      A.symw[k][1][a] = m->D[3][a] / (2.0 * m->w[a] * J * J);
+      A.wJ[k][a] = m->w[a] * J;
+    }
+  }
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) A.D[a][b] = m->D[a][b];
+  const double g1 = p->gamma[0], g2 = p->gamma[1];
+  A.xi1 = 1.0 / (g1 - 1.0);
+  A.xi2 = 1.0 / (g2 - 1.0);
+  A.pi1 = g1 * p->pinf[0] / (g1 - 1.0);
+  A.pi2 = g2 * p->pinf[1] / (g2 - 1.0);
+  A.gh1 = g1 / (g1 - 1.0);
+  A.gh2 = g2 / (g2 - 1.0);
+  A.pinf1 = p->pinf[0];
+  A.pinf2 = p->pinf[1];
+  A.rho01 = p->rho0[0];
+  A.rho02 = p->rho0[1];
+  A.Gamma = p->Gamma;
+  A.eps = p->eps;
+  A.GammaEps = p->Gamma * p->eps;
+  A.mu1 = p->mu[0];
+  A.mu2 = p->mu[1];
+  A.sigma = p->sigma;
+  A.has_grav = 0;
+  for (int k = 0; k < 3; ++k) {
+    A.grav[k] = k < m->dim ? p->g[k] : 0.0;
+    if (A.grav[k] != 0.0) A.has_grav = 1;
+  }
+  A.delta = p->grad_reg;
+  A.rk_a = 0.0;
+  A.rk_b = 1.0;
+  return A;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t g_bytes(const dg2p_mesh_s* m, const dg2p_params* p) {
+  const int C = viscous(p) ? 1 + m->dim : 1;
+  return align256(sizeof(double) * (size_t)(2 * m->dim) * C * (size_t)m->E * m->nfn);
+}
+size_t state_bytes(const dg2p_mesh_s* m) {
+  return align256(sizeof(double) * (size_t)m->nf * (size_t)m->E * m->nn);
+}
+size_t red_bytes() { return align256(sizeof(double) * (size_t)RED_BLOCKS * MON_SLOTS); }
+
+int red_blocks(const dg2p_mesh_s* m) {
+  const long long n = m->E * m->nn;
+  long long b = (n + RED_THREADS - 1) / RED_THREADS;
+  if (b > RED_BLOCKS) b = RED_BLOCKS;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+int check_ws(void* work, size_t need) {
+  if (need == 0) return DG2P_OK;
+  if (!work) return fail(DG2P_EWORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(work) & 255) return fail(DG2P_EWORKSPACE, "workspace is not 256-byte aligned");
+  return DG2P_OK;
+}
+
+template <int DIM, bool VISC>
+void launch_ingredients(const KArgs& A, const double* U, double* G, hipStream_t s) {
+  constexpr int EPW = 64 >> (2 * DIM);
+  const long long blocks = (A.E + EPW - 1) / EPW;
+  hipLaunchKernelGGL((k_face_ingredients<DIM, VISC>), dim3((unsigned)blocks), dim3(64), 0, s, A, U, G);
+}
+
+template <int DIM, bool VISC, bool CSF>
+void launch_stage(int mode, const KArgs& A, const double* Us, const double* G, const double* Un,
+                  double* Out, const double* dt, hipStream_t s) {
+  constexpr int EPW = 64 >> (2 * DIM);
+  const long long blocks = (A.E + EPW - 1) / EPW;
+  const dim3 g((unsigned)blocks), b(64);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, 0>), g, b, 0, s, A, Us, G, Un, Out, dt);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, 1>), g, b, 0, s, A, Us, G, Un, Out, dt);
+  else
+    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, 2>), g, b, 0, s, A, Us, G, Un, Out, dt);
+}
+
+template <int DIM>
+int residual_pass(int mode, const dg2p_mesh_s* m, const dg2p_params* p, KArgs& A, const double* Us,
+                  double* G, const double* Un, double* Out, const double* dt, hipStream_t s) {
+  const bool visc = viscous(p);
+  const bool csf = p->sigma != 0.0;
+  if (visc)
+    launch_ingredients<DIM, true>(A, Us, G, s);
+  else
+    launch_ingredients<DIM, false>(A, Us, G, s);
+  if (visc && csf)
+    launch_stage<DIM, true, true>(mode, A, Us, G, Un, Out, dt, s);
+  else if (visc)
+    launch_stage<DIM, true, false>(mode, A, Us, G, Un, Out, dt, s);
+  else if (csf)
+    launch_stage<DIM, false, true>(mode, A, Us, G, Un, Out, dt, s);
+  else
+    launch_stage<DIM, false, false>(mode, A, Us, G, Un, Out, dt, s);
+  (void)m;
+  return hip_check(hipGetLastError(), "stage launch");
+}
+
+int residual(int mode, const dg2p_mesh_s* m, const dg2p_params* p, KArgs& A, const double* Us,
+             double* G, const double* Un, double* Out, const double* dt, hipStream_t s) {
+  switch (m->dim) {
+    case 1: return residual_pass<1>(mode, m, p, A, Us, G, Un, Out, dt, s);
+    case 2: return residual_pass<2>(mode, m, p, A, Us, G, Un, Out, dt, s);
+    default: return residual_pass<3>(mode, m, p, A, Us, G, Un, Out, dt, s);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dg2p_version(void) { return "dg2p 0.1 (gfx950, p=3)"; }
+
+const char* dg2p_status_string(int status) {
+  switch (status) {
+    case DG2P_OK: return "DG2P_OK";
+    case DG2P_EINVAL: return "DG2P_EINVAL";
+    case DG2P_EHIP: return "DG2P_EHIP";
+    case DG2P_ENONPHYS: return "DG2P_ENONPHYS";
+    case DG2P_EUNSUPPORTED: return "DG2P_EUNSUPPORTED";
+    case DG2P_EWORKSPACE: return "DG2P_EWORKSPACE";
+    default: return "unknown status";
+  }
+}
+
+const char* dg2p_last_error(void) { return g_last_error.c_str(); }
+
+int dg2p_create_mesh(const dg2p_mesh_desc* desc, dg2p_mesh* out) {
+  g_last_error.clear();
+  if (!desc || !out) return fail(DG2P_EINVAL, "desc and out must be non-NULL");
+  *out = nullptr;
+  if (desc->dim < 1 || desc->dim > 3) return fail(DG2P_EINVAL, "dim must be 1, 2 or 3");
+  if (desc->order != 3) return fail(DG2P_EUNSUPPORTED, "only polynomial order 3 is implemented");
+  long long E = 1;
+  for (int k = 0; k < desc->dim; ++k) {
+    if (desc->n_elem[k] < 1) return fail(DG2P_EINVAL, "n_elem must be >= 1");
+    if (!(desc->hi[k] > desc->lo[k]) || !std::isfinite(desc->hi[k] - desc->lo[k]))
+      return fail(DG2P_EINVAL, "hi must exceed lo");
+    for (int s = 0; s < 2; ++s)
+      if (desc->bc[k][s] < DG2P_BC_PERIODIC || desc->bc[k][s] > DG2P_BC_EXTRAPOLATE)
+        return fail(DG2P_EINVAL, "unknown boundary kind");
+    if ((desc->bc[k][0] == DG2P_BC_PERIODIC) != (desc->bc[k][1] == DG2P_BC_PERIODIC))
+      return fail(DG2P_EINVAL, "periodic must be set on both sides of an axis");
+    E *= desc->n_elem[k];
+  }
+  const long long nn = 1LL << (2 * desc->dim);
+  if (E > (1LL << 40) / nn) return fail(DG2P_EINVAL, "mesh too large");
+  dg2p_mesh_s* m = new dg2p_mesh_s;
+  std::memset(m, 0, sizeof(*m));
+  m->desc = *desc;
+  m->dim = desc->dim;
+  m->E = E;
+  m->nn = (int)nn;
+  m->nf = desc->dim + 5;
+  m->nfn = (int)(nn / 4);
+  for (int k = 0; k < 3; ++k) {
+    m->N[k] = k < desc->dim ? desc->n_elem[k] : 1;
+    m->h[k] = k < desc->dim ? (desc->hi[k] - desc->lo[k]) / desc->n_elem[k] : 1.0;
+    m->J[k] = 0.5 * m->h[k];
+  }
+  gll3(m->xi, m->w, m->D);
+  *out = m;
+  return DG2P_OK;
+}
+
+int dg2p_destroy_mesh(dg2p_mesh m) {
+  delete m;
+  return DG2P_OK;
+}
+
+int dg2p_layout(dg2p_mesh m, int* n_fields, long long* n_elem, int* nodes_per_elem) {
+  if (!m) return fail(DG2P_EINVAL, "mesh is NULL");
+  if (n_fields) *n_fields = m->nf;
+  if (n_elem) *n_elem = m->E;
+  if (nodes_per_elem) *nodes_per_elem = m->nn;
+  return DG2P_OK;
+}
+
+int dg2p_node_coords(dg2p_mesh m, double* xyz) {
+  if (!m || !xyz) return fail(DG2P_EINVAL, "mesh and xyz must be non-NULL");
+  const long long E = m->E;
+  for (int k = 0; k < m->dim; ++k) {
+    long long stride = 1;
+    for (int kk = 0; kk < k; ++kk) stride *= m->N[kk];
+    for (long long e = 0; e < E; ++e) {
+      const long long ek = (e / stride) % m->N[k];
+      for (int j = 0; j < m->nn; ++j) {
+        const int a = (j >> (2 * k)) & 3;
+        xyz[((long long)k * E + e) * m->nn + j] =
+            m->desc.lo[k] + m->h[k] * (double)ek + m->J[k] * (m->xi[a] + 1.0);
+      }
+    }
+  }
+  return DG2P_OK;
+}
+
+int dg2p_workspace_size(dg2p_mesh m, const dg2p_params* p, int op, size_t* bytes) {
+  if (!m || !bytes) return fail(DG2P_EINVAL, "mesh and bytes must be non-NULL");
+  int st = check_params(m, p);
+  if (st) return st;
+  switch (op) {
+    case DG2P_OP_RHS: *bytes = g_bytes(m, p); break;
+    case DG2P_OP_RK_STEP: *bytes = g_bytes(m, p) + 2 * state_bytes(m); break;
+    case DG2P_OP_MAX_DT:
+    case DG2P_OP_MONITORS: *bytes = red_bytes(); break;
+    default: return fail(DG2P_EUNSUPPORTED, "operation not available in this build");
+  }
+  return DG2P_OK;
+}
+
+int dg2p_prim_to_cons(dg2p_mesh m, const dg2p_params* p, const double* prim, double* U, void* stream) {
+  g_last_error.clear();
+  if (!m || !prim || !U) return fail(DG2P_EINVAL, "mesh, prim and U must be non-NULL");
+  int st = check_params(m, p);
+  if (st) return st;
+  KArgs A = make_args(m, p);
+  const long long n = m->E * m->nn;
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  hipStream_t s = (hipStream_t)stream;
+  switch (m->dim) {
+    case 1: hipLaunchKernelGGL((k_prim_to_cons<1>), dim3(blocks), dim3(256), 0, s, A, prim, U, n); break;
+    case 2: hipLaunchKernelGGL((k_prim_to_cons<2>), dim3(blocks), dim3(256), 0, s, A, prim, U, n); break;
+    default: hipLaunchKernelGGL((k_prim_to_cons<3>), dim3(blocks), dim3(256), 0, s, A, prim, U, n); break;
+  }
+  return hip_check(hipGetLastError(), "prim_to_cons launch");
+}
+
+int dg2p_rhs(dg2p_mesh m, const dg2p_params* p, const double* U, double* R, void* work, void* stream) {
+  g_last_error.clear();
+  if (!m || !U || !R) return fail(DG2P_EINVAL, "mesh, U and R must be non-NULL");
+  if (U == R) return fail(DG2P_EINVAL, "U and R may not alias");
+  int st = check_params(m, p);
+  if (st) return st;
+  st = check_ws(work, g_bytes(m, p));
+  if (st) return st;
+  KArgs A = make_args(m, p);
+  double* G = static_cast<double*>(work);
+  return residual(0, m, p, A, U, G, nullptr, R, nullptr, (hipStream_t)stream);
+}
+
+int dg2p_max_dt(dg2p_mesh m, const dg2p_params* p, const double* U, double cfl, double* dt,
+                dg2p_monitors* mon, void* work, void* stream) {
+  g_last_error.clear();
+  if (!m || !U || (!dt && !mon)) return fail(DG2P_EINVAL, "mesh, U and one of dt/mon must be non-NULL");
+  if (!(cfl > 0.0)) return fail(DG2P_EINVAL, "cfl must be > 0");
+  int st = check_params(m, p);
+  if (st) return st;
+  st = check_ws(work, red_bytes());
+  if (st) return st;
+  KArgs A = make_args(m, p);
+  double* part = static_cast<double*>(work);
+  const int nb = red_blocks(m);
+  hipStream_t s = (hipStream_t)stream;
+  const bool v = viscous(p);
+  switch (m->dim) {
+    case 1:
+      if (v) hipLaunchKernelGGL((k_rate_partial<1, true>), dim3(nb), dim3(RED_THREADS), 0, s, A, U, part);
+      else hipLaunchKernelGGL((k_rate_partial<1, false>), dim3(nb), dim3(RED_THREADS), 0, s, A, U, part);
+      break;
+    case 2:
+      if (v) hipLaunchKernelGGL((k_rate_partial<2, true>), dim3(nb), dim3(RED_THREADS), 0, s, A, U, part);
+      else hipLaunchKernelGGL((k_rate_partial<2, false>), dim3(nb), dim3(RED_THREADS), 0, s, A, U, part);
+      break;
+    default:
+      if (v) hipLaunchKernelGGL((k_rate_partial<3, true>), dim3(nb), dim3(RED_THREADS), 0, s, A, U, part);
+      else hipLaunchKernelGGL((k_rate_partial<3, false>), dim3(nb), dim3(RED_THREADS), 0, s, A, U, part);
+      break;
+  }
+  double hmin = m->h[0];
+  for (int k = 1; k < m->dim; ++k) hmin = std::fmin(hmin, m->h[k]);
+  hipLaunchKernelGGL(k_rate_final, dim3(1), dim3(RED_THREADS), 0, s, part, nb, A.GammaEps, m->dim, hmin,
+                     cfl, dt, mon);
+  return hip_check(hipGetLastError(), "max_dt launch");
+}
+
+int dg2p_rk_step(dg2p_mesh m, const dg2p_params* p, double* U, const double* dt, void* work, void* stream) {
+  g_last_error.clear();
+  if (!m || !U || !dt) return fail(DG2P_EINVAL, "mesh, U and dt must be non-NULL");
+  int st = check_params(m, p);
+  if (st) return st;
+  st = check_ws(work, g_bytes(m, p) + 2 * state_bytes(m));
+  if (st) return st;
+  KArgs A = make_args(m, p);
+  char* w = static_cast<char*>(work);
+  double* G = reinterpret_cast<double*>(w);
+  double* U1 = reinterpret_cast<double*>(w + g_bytes(m, p));
+  double* U2 = reinterpret_cast<double*>(w + g_bytes(m, p) + state_bytes(m));
+  hipStream_t s = (hipStream_t)stream;
+  // stage 1: U1 = U + dt R(U)
+  st = residual(1, m, p, A, U, G, nullptr, U1, dt, s);
+  if (st) return st;
+  // stage 2: U2 = 3/4 U + 1/4 (U1 + dt R(U1))
+  A.rk_a = 0.75;
+  A.rk_b = 0.25;
+  st = residual(2, m, p, A, U1, G, U, U2, dt, s);
+  if (st) return st;
+  // stage 3: U <- 1/3 U + 2/3 (U2 + dt R(U2)); each node reads its own U before writing it
+  A.rk_a = 1.0 / 3.0;
+  A.rk_b = 2.0 / 3.0;
+  return residual(2, m, p, A, U2, G, U, U, dt, s);
+}
+
+int dg2p_compute_monitors(dg2p_mesh m, const dg2p_params* p, const double* U, double p_ref, const double* u_ref,
+                  dg2p_monitors* mon, void* work, void* stream) {
+  g_last_error.clear();
+  if (!m || !U || !mon) return fail(DG2P_EINVAL, "mesh, U and mon must be non-NULL");
+  int st = check_params(m, p);
+  if (st) return st;
+  st = check_ws(work, red_bytes());
+  if (st) return st;
+  KArgs A = make_args(m, p);
+  double ur[3] = {0.0, 0.0, 0.0};
+  if (u_ref)
+    for (int k = 0; k < m->dim; ++k) ur[k] = u_ref[k];
+  double* part = static_cast<double*>(work);
+  const int nb = red_blocks(m);
+  hipStream_t s = (hipStream_t)stream;
+  switch (m->dim) {
+    case 1:
+      hipLaunchKernelGGL((k_monitor_partial<1>), dim3(nb), dim3(RED_THREADS), 0, s, A, U, p_ref, ur[0], ur[1], ur[2], part);
+      hipLaunchKernelGGL((k_monitor_final<1>), dim3(1), dim3(64), 0, s, part, nb, mon);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_monitor_partial<2>), dim3(nb), dim3(RED_THREADS), 0, s, A, U, p_ref, ur[0], ur[1], ur[2], part);
+      hipLaunchKernelGGL((k_monitor_final<2>), dim3(1), dim3(64), 0, s, part, nb, mon);
+      break;
+    default:
+      hipLaunchKernelGGL((k_monitor_partial<3>), dim3(nb), dim3(RED_THREADS), 0, s, A, U, p_ref, ur[0], ur[1], ur[2], part);
+      hipLaunchKernelGGL((k_monitor_final<3>), dim3(1), dim3(64), 0, s, part, nb, mon);
+      break;
+  }
+  st = hip_check(hipGetLastError(), "monitor launch");
+  if (st) return st;
+  // max_rate is part of the monitor record: reuse the rate reduction (writes mon->max_rate / mon->dt)
+  return dg2p_max_dt(m, p, U, 0.1, nullptr, mon, static_cast<char*>(work), stream);
+}
+
+}  // extern "C"

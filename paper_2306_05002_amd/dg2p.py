@@ -1,0 +1,272 @@
+"""Thin ctypes binding of libdg2p (the C ABI of include/dg2p.h).
+
+Argument marshalling only: every step of the residual, the RK stages, the
+time-step reduction, the monitors and the initial-condition map runs in the
+library's HIP kernels.  Torch provides device memory (tensors), streams and
+the workspace buffers.  Importing this module loads ``libdg2p.so`` from the
+package directory and raises ImportError if it is missing: there is no
+fallback path.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdg2p.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libdg2p.so not built at {LIB_PATH}; run __graft_entry__.build()")
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, EINVAL, EHIP, ENONPHYS, EUNSUPPORTED, EWORKSPACE = 0, -1, -2, -3, -4, -5
+BC = {"periodic": 0, "slip_wall": 1, "dirichlet": 2, "extrapolate": 3}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
+OP_RHS, OP_RK_STEP, OP_MAX_DT, OP_MONITORS, OP_RHS_VJP, OP_RK_STEP_VJP = range(6)
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("order", ctypes.c_int),
+                ("n_elem", ctypes.c_int * 3),
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("bc", (ctypes.c_int * 2) * 3),
+                ("bc_state", ((ctypes.c_double * 8) * 2) * 3)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double * 2), ("pinf", ctypes.c_double * 2),
+                ("rho0", ctypes.c_double * 2), ("Gamma", ctypes.c_double),
+                ("eps", ctypes.c_double), ("mu", ctypes.c_double * 2),
+                ("sigma", ctypes.c_double), ("g", ctypes.c_double * 3),
+                ("c_ip", ctypes.c_double), ("grad_reg", ctypes.c_double),
+                ("precision", ctypes.c_int)]
+
+
+class Monitors(ctypes.Structure):
+    _fields_ = [("max_rate", ctypes.c_double), ("dt", ctypes.c_double),
+                ("min_alpha", ctypes.c_double), ("max_alpha", ctypes.c_double),
+                ("integral", ctypes.c_double * 8), ("dev_p", ctypes.c_double),
+                ("dev_u", ctypes.c_double), ("nonphys", ctypes.c_longlong)]
+
+
+MONITOR_DOUBLES = ctypes.sizeof(Monitors) // 8
+
+_vp, _dp, _i, _d = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+_SIG = {
+    "dg2p_version": ([], ctypes.c_char_p),
+    "dg2p_status_string": ([_i], ctypes.c_char_p),
+    "dg2p_last_error": ([], ctypes.c_char_p),
+    "dg2p_create_mesh": ([ctypes.POINTER(MeshDesc), ctypes.POINTER(ctypes.c_void_p)], _i),
+    "dg2p_destroy_mesh": ([_vp], _i),
+    "dg2p_layout": ([_vp, ctypes.POINTER(_i), ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_i)], _i),
+    "dg2p_node_coords": ([_vp, _dp], _i),
+    "dg2p_workspace_size": ([_vp, ctypes.POINTER(Params), _i, ctypes.POINTER(ctypes.c_size_t)], _i),
+    "dg2p_prim_to_cons": ([_vp, ctypes.POINTER(Params), _dp, _dp, _vp], _i),
+    "dg2p_rhs": ([_vp, ctypes.POINTER(Params), _dp, _dp, _vp, _vp], _i),
+    "dg2p_max_dt": ([_vp, ctypes.POINTER(Params), _dp, _d, _dp, _vp, _vp, _vp], _i),
+    "dg2p_rk_step": ([_vp, ctypes.POINTER(Params), _dp, _dp, _vp, _vp], _i),
+    "dg2p_compute_monitors": ([_vp, ctypes.POINTER(Params), _dp, _d, _dp, _vp, _vp, _vp], _i),
+}
+for _name, (_args, _res) in _SIG.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = _res
+
+
+class Dg2pError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        detail = _lib.dg2p_last_error().decode()
+        name = _lib.dg2p_status_string(status).decode()
+        super().__init__(f"{what}: {name} ({detail})")
+
+
+def _check(status, what):
+    if status != OK:
+        raise Dg2pError(status, what)
+
+
+def version():
+    return _lib.dg2p_version().decode()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_params(p, precision="fp64"):
+    """dg2p_params from a dict with keys gamma, pinf, rho0, Gamma, eps, mu,
+    sigma, g, c_ip, grad_reg (the workloads module's parameter dict)."""
+    P = Params()
+    P.gamma[:] = list(p["gamma"])
+    P.pinf[:] = list(p["pinf"])
+    P.rho0[:] = list(p["rho0"])
+    P.Gamma = p["Gamma"]
+    P.eps = p["eps"]
+    P.mu[:] = list(p.get("mu", (0.0, 0.0)))
+    P.sigma = p.get("sigma", 0.0)
+    g = list(p.get("g", (0.0, 0.0, 0.0))) + [0.0, 0.0, 0.0]
+    P.g[:] = g[:3]
+    P.c_ip = p.get("c_ip", 1.0)
+    P.grad_reg = p.get("grad_reg", 1e-12)
+    P.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    return P
+
+
+class Mesh:
+    """Owning wrapper of a dg2p_mesh handle plus cached workspaces."""
+
+    def __init__(self, dim, n_elem, lo, hi, bc=None, bc_state=None, order=3):
+        d = MeshDesc()
+        d.dim = dim
+        d.order = order
+        for k in range(3):
+            have = k < min(dim, len(n_elem))
+            d.n_elem[k] = int(n_elem[k]) if have else 1
+            d.lo[k] = float(lo[k]) if have else 0.0
+            d.hi[k] = float(hi[k]) if have else 1.0
+            for s in range(2):
+                kind = bc[k][s] if (bc is not None and k < min(dim, len(bc))) else "periodic"
+                d.bc[k][s] = BC[kind] if isinstance(kind, str) else int(kind)
+                vals = (bc_state or {}).get((k, s))
+                if vals is not None:
+                    for f, v in enumerate(list(vals)[:8]):
+                        d.bc_state[k][s][f] = float(v)
+        h = ctypes.c_void_p()
+        _check(_lib.dg2p_create_mesh(ctypes.byref(d), ctypes.byref(h)), "dg2p_create_mesh")
+        self._h = h
+        self.desc = d
+        self.dim = dim
+        nf, E, nn = ctypes.c_int(), ctypes.c_longlong(), ctypes.c_int()
+        _check(_lib.dg2p_layout(h, ctypes.byref(nf), ctypes.byref(E), ctypes.byref(nn)), "dg2p_layout")
+        self.nf, self.E, self.nn = nf.value, E.value, nn.value
+        self._ws = {}
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self, _destroy=_lib.dg2p_destroy_mesh):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _destroy(h)
+            self._h = None
+
+    def state_shape(self):
+        return (self.nf, self.E, self.nn)
+
+    def node_coords(self):
+        out = np.empty((self.dim, self.E, self.nn), dtype=np.float64)
+        _check(_lib.dg2p_node_coords(self._h, out.ctypes.data_as(ctypes.c_void_p)), "dg2p_node_coords")
+        return out
+
+    def workspace_bytes(self, params, op):
+        n = ctypes.c_size_t()
+        _check(_lib.dg2p_workspace_size(self._h, ctypes.byref(params), op, ctypes.byref(n)),
+               "dg2p_workspace_size")
+        return n.value
+
+    def workspace(self, params, op, device):
+        """Device workspace for an operation (cached per op, grown on demand)."""
+        need = self.workspace_bytes(params, op)
+        key = (op, str(device))
+        buf = self._ws.get(key)
+        if buf is None or buf.numel() < need + 256:
+            buf = torch.empty(max(need + 256, 256), dtype=torch.uint8, device=device)
+            self._ws[key] = buf
+        off = (-buf.data_ptr()) % 256
+        return ctypes.c_void_p(buf.data_ptr() + off) if need else None
+
+
+def _as_state(mesh, U):
+    if U.dtype != torch.float64 or not U.is_cuda or not U.is_contiguous():
+        raise ValueError("state must be a contiguous float64 CUDA tensor")
+    if tuple(U.shape) != mesh.state_shape():
+        raise ValueError(f"state shape {tuple(U.shape)} != {mesh.state_shape()}")
+    return U
+
+
+def prim_to_cons(mesh, params, prim, stream=None):
+    prim = _as_state(mesh, prim)
+    U = torch.empty_like(prim)
+    _check(_lib.dg2p_prim_to_cons(mesh.handle, ctypes.byref(params), _ptr(prim), _ptr(U),
+                                  _stream(stream)), "dg2p_prim_to_cons")
+    return U
+
+
+def rhs(mesh, params, U, out=None, stream=None):
+    U = _as_state(mesh, U)
+    R = torch.empty_like(U) if out is None else out
+    ws = mesh.workspace(params, OP_RHS, U.device)
+    _check(_lib.dg2p_rhs(mesh.handle, ctypes.byref(params), _ptr(U), _ptr(R), ws, _stream(stream)),
+           "dg2p_rhs")
+    return R
+
+
+def max_dt(mesh, params, U, cfl=0.1, dt=None, stream=None):
+    """Device scalar dt = cfl / max_rate (no host synchronisation)."""
+    U = _as_state(mesh, U)
+    if dt is None:
+        dt = torch.empty(1, dtype=torch.float64, device=U.device)
+    ws = mesh.workspace(params, OP_MAX_DT, U.device)
+    _check(_lib.dg2p_max_dt(mesh.handle, ctypes.byref(params), _ptr(U), float(cfl), _ptr(dt), None, ws,
+                            _stream(stream)), "dg2p_max_dt")
+    return dt
+
+
+def rk_step(mesh, params, U, dt, stream=None):
+    """One SSP-RK3 step, in place on U; dt is a 1-element float64 device tensor."""
+    U = _as_state(mesh, U)
+    ws = mesh.workspace(params, OP_RK_STEP, U.device)
+    _check(_lib.dg2p_rk_step(mesh.handle, ctypes.byref(params), _ptr(U), _ptr(dt), ws, _stream(stream)),
+           "dg2p_rk_step")
+    return U
+
+
+def monitors(mesh, params, U, p_ref=0.0, u_ref=None, stream=None, sync=True):
+    U = _as_state(mesh, U)
+    buf = torch.zeros(MONITOR_DOUBLES, dtype=torch.float64, device=U.device)
+    ur = (ctypes.c_double * 3)(*([0.0, 0.0, 0.0] if u_ref is None else (list(u_ref) + [0.0] * 3)[:3]))
+    ws = mesh.workspace(params, OP_MONITORS, U.device)
+    _check(_lib.dg2p_compute_monitors(mesh.handle, ctypes.byref(params), _ptr(U), float(p_ref),
+                                      ctypes.cast(ur, ctypes.c_void_p), _ptr(buf), ws, _stream(stream)),
+           "dg2p_compute_monitors")
+    if not sync:
+        return buf
+    raw = buf.cpu().numpy()
+    m = Monitors.from_buffer_copy(raw.tobytes())
+    return dict(max_rate=m.max_rate, dt=m.dt, min_alpha=m.min_alpha, max_alpha=m.max_alpha,
+                integral=list(m.integral)[:mesh.nf], dev_p=m.dev_p, dev_u=m.dev_u,
+                nonphys=int(m.nonphys))
+
+
+def mesh_from_config(cfg, params=None):
+    """Mesh for a workloads configuration; Dirichlet states are mapped to
+    conserved variables with the library's own initial-condition kernel."""
+    d = cfg["dim"]
+    bc_state = {}
+    if cfg.get("bc_prim"):
+        P = make_params(cfg["params"]) if params is None else params
+        probe = Mesh(d, (1,) * d, (0.0,) * d, (1.0,) * d)
+        for key, bp in cfg["bc_prim"].items():
+            vals = [bp["alpha"], bp["psi"], bp["rho1"], bp["rho2"]] + list(bp["u"][:d]) + [bp["P"]]
+            prim = torch.tensor(vals, dtype=torch.float64, device="cuda")[:, None, None]
+            prim = prim.expand(probe.nf, 1, probe.nn).contiguous()
+            Uc = prim_to_cons(probe, P, prim)
+            bc_state[key] = Uc[:, 0, 0].cpu().tolist()
+    return Mesh(d, cfg["n_elem"], cfg["lo"], cfg["hi"], cfg["bc"], bc_state, order=cfg["order"])
+
+
+def prim_tensor(pf, d, device="cuda"):
+    """Stack the workloads primitive dict into the library's primitive layout."""
+    arrs = [pf["alpha"], pf["psi"], pf["rho1"], pf["rho2"]] + [pf["u"][j] for j in range(d)] + [pf["P"]]
+    host = np.stack([np.ascontiguousarray(a, dtype=np.float64) for a in arrs])
+    return torch.from_numpy(host).to(device)

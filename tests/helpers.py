@@ -34,6 +34,20 @@ def cons_from_prim(pf, prm):
                                T(pf["rho2"]), T(pf["u"]), T(pf["P"]), prm)
 
 
+def field_scales(U, d, prm):
+    """Magnitude of each field for the parity metric: max|U_f|, except the
+    momentum components, which use the momentum-flux scale max rho (|u| + c)
+    (a momentum component can be identically zero, e.g. the transverse one of
+    a planar shock, while its residual carries pressure round-off)."""
+    pr = oracle.primitives(U, d, prm)
+    speed = torch.sqrt((pr["u"] ** 2).sum(0)) + pr["c"]
+    mom = float((pr["rho"] * speed).max())
+    out = []
+    for f in range(U.shape[0]):
+        out.append(mom if 2 <= f < 2 + d else float(U[f].abs().max()))
+    return out
+
+
 def rel_err_fields(X, Y, scale):
     """Per-field normwise error max|X - Y| / max(max|Y|, scale_f)."""
     out = []

@@ -1,0 +1,229 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Metric (per field f): e_f = max|X_gpu - X_oracle| / max(max|X_oracle|, S_f)
+with S_f = M_f * rate for residuals (rate = the time-step rule's largest
+rate, i.e. the size of R that a state of that magnitude can produce) and
+S_f = M_f for states, where M_f = max|U_f| except for momentum components,
+M_f = max rho (|u| + c) (a momentum component may vanish identically while
+its residual carries pressure round-off).  Bar: e_f <= 1e-12 for FP64.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from helpers import oracle_setup, field_scales
+from paper_2306_05002_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _dg():
+    from paper_2306_05002_amd import dg2p
+    return dg2p
+
+
+def gpu_case(name, n_elem=None, variant=None, **over):
+    cfg, om, prm, U0 = oracle_setup(name, n_elem=n_elem, variant=variant, **over)
+    dg = _dg()
+    P = dg.make_params({**cfg["params"], **over})
+    mesh = dg.mesh_from_config(dict(cfg, params={**cfg["params"], **over}), P)
+    return cfg, om, prm, U0, mesh, P
+
+
+def res_errors(Rg, Ro, U, rate, prm, d):
+    out = []
+    M = field_scales(U, d, prm)
+    for f in range(U.shape[0]):
+        den = max(float(Ro[f].abs().max()), M[f] * rate)
+        out.append(float((Rg[f] - Ro[f]).abs().max()) / den)
+    return out
+
+
+def state_errors(Ug, Uo, prm, d):
+    M = field_scales(Uo, d, prm)
+    return [float((Ug[f] - Uo[f]).abs().max()) / max(float(Uo[f].abs().max()), M[f], 1e-300)
+            for f in range(Uo.shape[0])]
+
+
+SMALL = [
+    ("drop1d", None, None),
+    ("drop1d", None, "noisy_u"),
+    ("drop1d", (37,), "noisy_u"),      # ragged: 37 elements, 16 per wave
+    ("drop1d", (1,), None),            # single element, its own periodic neighbour
+    ("drop2d", (12, 10), None),
+    ("drop2d", (7, 5), None),          # ragged: 35 elements, 4 per wave
+    ("drop2d", (1, 1), None),
+    ("shock2d", (16, 8), None),        # Dirichlet inflow, extrapolated outflow
+    ("shock2d", (13, 7), None),
+    ("adjoint2d", (10, 9), None),      # viscous + CSF
+    ("rt3d", (5, 4, 6), None),         # viscous + CSF + gravity + slip walls
+    ("rt3d", (1, 1, 2), None),
+]
+
+
+@pytest.mark.parametrize("name,ne,variant", SMALL)
+def test_rhs_parity(name, ne, variant):
+    cfg, om, prm, U0, mesh, P = gpu_case(name, ne, variant)
+    dg = _dg()
+    Ro = oracle.rhs(U0, om, prm)
+    Rg = dg.rhs(mesh, P, U0.cuda().contiguous()).cpu()
+    rate = oracle.max_rate(U0, om, prm)
+    errs = res_errors(Rg, Ro, U0, rate, prm, om.d)
+    print(name, ne, variant, ["%.1e" % e for e in errs])
+    assert max(errs) <= TOL, errs
+
+
+@pytest.mark.parametrize("name,ne,steps", [("drop1d", None, 100), ("drop2d", (8, 8), 30),
+                                           ("rt3d", (4, 4, 4), 10), ("adjoint2d", (8, 8), 20)])
+def test_rhs_parity_evolved_state(name, ne, steps):
+    """Parity on a state the oracle has advanced (not an initial condition)."""
+    cfg, om, prm, U0, mesh, P = gpu_case(name, ne, "noisy_u" if name == "drop1d" else None)
+    dt = oracle.max_dt(U0, om, prm)
+    U = U0
+    for _ in range(steps):
+        U = oracle.rk_step(U, dt, om, prm)
+    Ro = oracle.rhs(U, om, prm)
+    Rg = _dg().rhs(mesh, P, U.cuda().contiguous()).cpu()
+    errs = res_errors(Rg, Ro, U, oracle.max_rate(U, om, prm), prm, om.d)
+    assert max(errs) <= TOL, errs
+
+
+@pytest.mark.parametrize("name,ne", [("drop1d", (37,)), ("drop2d", (7, 5)), ("shock2d", (13, 7)),
+                                     ("adjoint2d", (6, 5)), ("rt3d", (3, 4, 5))])
+def test_rk_step_and_dt_parity(name, ne):
+    cfg, om, prm, U0, mesh, P = gpu_case(name, ne)
+    dg = _dg()
+    Ud = U0.cuda().contiguous()
+    dt = dg.max_dt(mesh, P, Ud, cfl=0.1)
+    dto = oracle.max_dt(U0, om, prm, cfl=0.1)
+    assert abs(float(dt.cpu()) - dto) <= TOL * dto
+    dg.rk_step(mesh, P, Ud, dt)
+    U1 = oracle.rk_step(U0, float(dt.cpu()), om, prm)
+    errs = state_errors(Ud.cpu(), U1, prm, om.d)
+    assert max(errs) <= TOL, errs
+
+
+@pytest.mark.parametrize("name,ne", [("drop2d", (9, 6)), ("rt3d", (3, 3, 4)), ("shock2d", (10, 5))])
+def test_monitors_parity(name, ne):
+    cfg, om, prm, U0, mesh, P = gpu_case(name, ne)
+    d = cfg["dim"]
+    u_ref = [1.0, 0.5, 0.0][:d]
+    mg = _dg().monitors(mesh, P, U0.cuda().contiguous(), p_ref=1.0, u_ref=u_ref)
+    mo = oracle.monitors(U0, om, prm, p_ref=1.0, u_ref=u_ref)
+    for f in range(om.nf):
+        a, b = mg["integral"][f], float(mo["integral"][f])
+        scale = float((U0[f].abs() * om.node_weights()).sum()) + 1e-300
+        assert abs(a - b) <= TOL * scale, (f, a, b)
+    assert mg["min_alpha"] == mo["min_alpha"] and mg["max_alpha"] == mo["max_alpha"]
+    assert mg["nonphys"] == mo["nonphys"]
+    assert abs(mg["max_rate"] - mo["max_rate"]) <= TOL * mo["max_rate"]
+    assert abs(mg["dev_p"] - mo["dev_p"]) <= 1e-12 * max(1.0, mo["dev_p"])
+    assert abs(mg["dev_u"] - mo["dev_u"]) <= 1e-12 * max(1.0, mo["dev_u"])
+
+
+def test_monitors_count_nonphysical_nodes():
+    """Injected bad nodes (NaN, negative density, P + Pinf < 0) are counted."""
+    cfg, om, prm, U0, mesh, P = gpu_case("drop2d", (4, 4))
+    U = U0.clone()
+    U[0, 3, 5] = float("nan")
+    U[0, 7, 1] = -5.0
+    U[1, 7, 1] = 0.0
+    U[4, 9, 9] = -50.0            # energy far below the stiffened-gas floor
+    mg = _dg().monitors(mesh, P, U.cuda().contiguous())
+    mo = oracle.monitors(U, om, prm)
+    assert mg["nonphys"] == mo["nonphys"] == 3
+
+
+@pytest.mark.parametrize("name,ne", [("drop1d", (23,)), ("drop2d", (5, 6)), ("rt3d", (2, 3, 2))])
+def test_prim_to_cons_parity(name, ne):
+    cfg = workloads.config(name, n_elem=ne)
+    dg = _dg()
+    P = dg.make_params(cfg["params"])
+    mesh = dg.mesh_from_config(cfg, P)
+    om = oracle.OracleMesh(cfg["dim"], 3, ne, cfg["lo"], cfg["hi"], cfg["bc"])
+    X = om.node_coords().numpy()
+    pf = workloads.primitive_fields(cfg, X)
+    prm = oracle.Params(**cfg["params"])
+    from helpers import cons_from_prim
+    Uo = cons_from_prim(pf, prm)
+    Ug = dg.prim_to_cons(mesh, P, dg.prim_tensor(pf, cfg["dim"])).cpu()
+    assert max(state_errors(Ug, Uo, prm, cfg["dim"])) <= 1e-15
+
+
+def test_determinism_bitwise():
+    cfg, om, prm, U0, mesh, P = gpu_case("rt3d", (4, 3, 4))
+    dg = _dg()
+    Ud = U0.cuda().contiguous()
+    R1 = dg.rhs(mesh, P, Ud).clone()
+    R2 = dg.rhs(mesh, P, Ud).clone()
+    assert torch.equal(R1, R2)
+    A, B = Ud.clone(), Ud.clone()
+    dt = dg.max_dt(mesh, P, Ud)
+    dg.rk_step(mesh, P, A, dt)
+    dg.rk_step(mesh, P, B, dt)
+    assert torch.equal(A, B)
+
+
+def test_interface_equilibrium_on_gpu():
+    """50 GPU SSP-RK3 steps of the droplet keep P and u uniform to round-off
+    and conserve both phase masses, momentum and energy."""
+    cfg, om, prm, U0, mesh, P = gpu_case("drop2d", (16, 16))
+    dg = _dg()
+    U = U0.cuda().contiguous()
+    m0 = dg.monitors(mesh, P, U, p_ref=1.0, u_ref=[1.0, 0.5])
+    for _ in range(50):
+        dt = dg.max_dt(mesh, P, U)
+        dg.rk_step(mesh, P, U, dt)
+    m1 = dg.monitors(mesh, P, U, p_ref=1.0, u_ref=[1.0, 0.5])
+    assert m1["dev_p"] < 1e-12 and m1["dev_u"] < 1e-12, m1
+    assert m1["nonphys"] == 0
+    for f in range(5):
+        assert abs(m1["integral"][f] - m0["integral"][f]) <= 1e-13 * abs(m0["integral"][f]) + 1e-15
+
+
+FULL = ["drop2d", "shock2d", "adjoint2d", "rt3d"]
+
+
+def _sample_elements(cfg, n=48, seed=0):
+    """Sampled element indices: corners and boundary layers plus random ones."""
+    N = cfg["n_elem"]
+    E = int(np.prod(N))
+    rng = np.random.default_rng(seed)
+    picks = set(rng.integers(0, E, n).tolist())
+    d = len(N)
+    for corner in range(2 ** d):
+        c = [(N[k] - 1) if (corner >> k) & 1 else 0 for k in range(d)]
+        e = 0
+        stride = 1
+        for k in range(d):
+            e += c[k] * stride
+            stride *= N[k]
+        picks.add(e)
+    return torch.tensor(sorted(picks), dtype=torch.long)
+
+
+@pytest.mark.parametrize("name", FULL)
+def test_full_size_sampled_parity(name):
+    """Full-size grid, the launch shapes the benchmark times: GPU residual on
+    every element, oracle on sampled elements (one by one)."""
+    cfg, om, prm, U0, mesh, P = gpu_case(name)
+    dg = _dg()
+    Ud = U0.cuda().contiguous()
+    Rg = dg.rhs(mesh, P, Ud)
+    el = _sample_elements(cfg)
+    Ro = oracle.rhs(U0, om, prm, elems=el)
+    Rs = Rg[:, el.cuda()].cpu()
+    rate = oracle.max_rate(U0, om, prm)
+    errs = res_errors(Rs, Ro, U0, rate, prm, om.d)
+    print(name, ["%.1e" % e for e in errs])
+    assert max(errs) <= TOL, errs
+    dt = dg.max_dt(mesh, P, Ud)
+    assert abs(float(dt.cpu()) - 0.1 / rate) <= TOL * 0.1 / rate
+    del Rg, Ud
+    torch.cuda.empty_cache()
