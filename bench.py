@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Benchmark: DOF-updates/s of the DG SSP-RK3 stage on one MI355X.
+
+One step = one pass of the whole hot path on the workload: the time-step
+reduction (dg2p_max_dt, device scalar dt) and one SSP-RK3 step
+(dg2p_rk_step: three residual + stage-combine passes), state resident in HBM.
+value = 3 * N_nodes * N_fields / (seconds per step).
+
+The JSON line also carries
+  roofline:     algorithmic bytes of the stage kernel per launch (21.33 B per
+                DOF per stage, averaged over the three stages: stage 1 reads
+                U^n and writes U^1, stages 2 and 3 read U^n and U^s and write
+                U^{s+1}) divided by its mean launch duration, measured with
+                hipEvents the library records around its own launches on the
+                launch stream; HBM peak 8 TB/s.  `traffic` is the counter-
+                measured HBM traffic per launch recorded under profiles/ for
+                the current kernel sources (null if the sources changed).
+  cpu_baseline: the FP64 CPU oracle's residual evaluations on the host cores
+                over a bounded sample of the same workload.
+
+--gpus N with N > 1 is refused: this build runs on one GPU.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD_DESC = {
+    "drop1d": "1D periodic air/water slab, 100 elements, p=3, FP64",
+    "drop2d": "2D periodic water droplet in air, 128x128 quads, p=3, FP64",
+    "shock2d": "2D shock onto water cylinder, 512x256 quads, p=3, FP64",
+    "rt3d": "3D heavy-over-light box, 96^3 hexahedra, p=3, viscous + CSF + gravity, FP64",
+    "adjoint2d": "2D droplet 128x128 p=3, viscous + CSF, FP64 forward",
+}
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2306_05002_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(workload, src_hash):
+    """HBM bytes per stage-kernel launch from the committed counter summary,
+    if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"k_stage_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha256_16") != src_hash:
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(cfg, seconds):
+    """FP64 oracle residual evaluations on the host, bounded to ~`seconds`."""
+    import numpy as np
+    import torch
+    import oracle
+
+    prm = oracle.Params(**cfg["params"])
+    d = cfg["dim"]
+    bc_state = {}
+    for key, bp in cfg.get("bc_prim", {}).items():
+        t = lambda v: torch.tensor([float(v)], dtype=torch.float64)
+        Qb = oracle.prim_to_cons(t(bp["alpha"]), t(bp["psi"]), t(bp["rho1"]), t(bp["rho2"]),
+                                 torch.tensor(bp["u"][:d], dtype=torch.float64)[:, None],
+                                 t(bp["P"]), prm)
+        bc_state[key] = Qb[:, 0]
+    om = oracle.OracleMesh(d, cfg["order"], cfg["n_elem"], cfg["lo"], cfg["hi"], cfg["bc"], bc_state)
+    # bounded sample: at most 16384 elements (the whole grid when it is smaller)
+    n_s = min(om.E, 16384)
+    el = torch.arange(n_s)
+    from paper_2306_05002_amd import workloads
+    X = om.node_coords()
+    pf = workloads.primitive_fields(cfg, X.numpy())
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64)
+    U = oracle.prim_to_cons(T(pf["alpha"]), T(pf["psi"]), T(pf["rho1"]), T(pf["rho2"]),
+                            T(pf["u"]), T(pf["P"]), prm)
+    oracle.rhs(U, om, prm, elems=el)
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        oracle.rhs(U, om, prm, elems=el)
+        reps += 1
+        el_t = time.perf_counter() - t0
+        if el_t >= seconds or reps >= 200:
+            break
+    dof = n_s * om.nn * om.nf
+    sample = (f"oracle residual (one RK stage's work) on {n_s} of {om.E} elements, "
+              f"{reps} evaluations, {el_t:.1f} s")
+    return dict(value=dof * reps / el_t, unit="DOF-updates/s", cores=torch.get_num_threads(),
+                kind="oracle", sample=sample)
+
+
+def calibrate_copy(gib=2.0, reps=10):
+    """Plain copy kernel of known size (reads and writes `gib` GiB) for
+    scaling the HBM counters of the profiler."""
+    import torch
+    n = int(gib * (1 << 30) / 8)
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_read": n * 8, "bytes_written": n * 8, "launches": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="drop2d", choices=sorted(WORKLOAD_DESC))
+    ap.add_argument("--cfl", type=float, default=0.1)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (--gpus 1); no multi-GPU path exists",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+
+    import torch
+    from paper_2306_05002_amd import dg2p, workloads
+
+    cfg = workloads.config(args.workload)
+    P = dg2p.make_params(cfg["params"])
+    mesh = dg2p.mesh_from_config(cfg, P)
+    pf = workloads.primitive_fields(cfg, mesh.node_coords())
+    U = dg2p.prim_to_cons(mesh, P, dg2p.prim_tensor(pf, cfg["dim"]))
+    del pf
+    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+    n_nodes = mesh.E * mesh.nn
+    dof = n_nodes * mesh.nf
+
+    def step():
+        dg2p.max_dt(mesh, P, U, cfl=args.cfl, dt=dt)
+        dg2p.rk_step(mesh, P, U, dt)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = e0.elapsed_time(e1) / args.steps
+    value = 3.0 * dof / (ms_step * 1e-3)
+
+    mon = dg2p.monitors(mesh, P, U)
+
+    # per-kernel durations from library-recorded hipEvents on the launch stream
+    n_prof = max(1, min(args.steps, 30))
+    dg2p.timing_enable(True)
+    for _ in range(n_prof):
+        step()
+    torch.cuda.synchronize()
+    dg2p.timing_enable(False)
+    k_ms = {}
+    for name, kind in (("stage", dg2p.K_STAGE), ("ingredients", dg2p.K_INGREDIENTS),
+                       ("rate", dg2p.K_RATE), ("rate_final", dg2p.K_RATE_FINAL)):
+        k_ms[name] = dg2p.timing_read(kind)
+    stage_ms = k_ms["stage"][0]
+    alg_bytes = (64.0 / 3.0) * dof          # per stage launch, averaged over the 3 stages
+    achieved = alg_bytes / (stage_ms * 1e-3) / 1e9
+    src = source_hash()
+    traffic = recorded_traffic(args.workload, src)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cfg, args.cpu_seconds)
+
+    out = {
+        "metric": "DOF-updates/s of DG RK stage, FP64 vs mixed vs adjoint, at stated error",
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {WORKLOAD_DESC[args.workload]}",
+            "n_elem": list(cfg["n_elem"]),
+            "order": cfg["order"],
+            "nodes": n_nodes,
+            "fields": mesh.nf,
+            "dof": dof,
+            "precision": "fp64",
+            "step": "max_dt + SSP-RK3 (3 stages)",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "k_stage (residual + stage combine)",
+            "kernel_mean_ms": stage_ms,
+            "algorithmic_bytes_per_launch": alg_bytes,
+        },
+        "kernels_mean_ms": {k: v[0] for k, v in k_ms.items()},
+        "cpu_baseline": cpu,
+        "monitors": {"nonphys": mon["nonphys"], "min_alpha": mon["min_alpha"],
+                     "max_alpha": mon["max_alpha"]},
+        "wall_s_timed": wall,
+        "source_sha256_16": src,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

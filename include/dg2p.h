@@ -180,6 +180,27 @@ int dg2p_compute_monitors(dg2p_mesh m, const dg2p_params* p /*host*/, const doub
                   double p_ref, const double* u_ref /*host, d values*/,
                   dg2p_monitors* mon /*device*/, void* work /*device*/, void* stream);
 
+/* Kernel kinds of the timing facility. */
+typedef enum {
+  DG2P_K_INGREDIENTS = 0, /* face-ingredient pass (neighbour interface flux / traction) */
+  DG2P_K_STAGE = 1,       /* residual + RK stage combine */
+  DG2P_K_RATE = 2,        /* time-step rate reduction, first pass */
+  DG2P_K_RATE_FINAL = 3,  /* time-step rate reduction, final pass */
+  DG2P_K_MONITOR = 4,     /* monitor reduction */
+  DG2P_K_PRIM = 5         /* initial-condition map */
+} dg2p_kernel_kind;
+
+/* Benchmark timing.  While enabled, every kernel the library launches is
+ * bracketed by a pair of library-owned hipEvents recorded on its stream (at
+ * most 8192 launches per enable; enabling resets the record).  The events
+ * are created on the first enable (host call, no device allocation).
+ * Not thread-safe: for single-threaded benchmark drivers. */
+int dg2p_timing_enable(int on);
+
+/* Mean duration (ms) and count of the recorded launches of one kernel kind;
+ * synchronises on the recorded events (host blocking). */
+int dg2p_timing_read(int kernel, double* mean_ms /*host*/, long long* count /*host*/);
+
 #ifdef __cplusplus
 }
 #endif

@@ -140,6 +140,32 @@ KArgs make_args(const dg2p_mesh_s* m, const dg2p_params* p) {
   return A;
 }
 
+// ---- optional kernel timing (benchmarks): library-owned event pairs ----
+constexpr int TIMING_SLOTS = 8192;
+struct Timing {
+  bool on = false;
+  int used = 0;
+  hipEvent_t start[TIMING_SLOTS];
+  hipEvent_t stop[TIMING_SLOTS];
+  int kind[TIMING_SLOTS];
+  bool created = false;
+};
+Timing g_timing;
+
+struct TimedLaunch {
+  int slot = -1;
+  hipStream_t s;
+  TimedLaunch(int kind, hipStream_t st) : s(st) {
+    if (!g_timing.on || g_timing.used >= TIMING_SLOTS) return;
+    slot = g_timing.used++;
+    g_timing.kind[slot] = kind;
+    (void)hipEventRecord(g_timing.start[slot], s);
+  }
+  ~TimedLaunch() {
+    if (slot >= 0) (void)hipEventRecord(g_timing.stop[slot], s);
+  }
+};
+
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 size_t g_bytes(const dg2p_mesh_s* m, const dg2p_params* p) {
@@ -170,6 +196,7 @@ template <int DIM, bool VISC>
 void launch_ingredients(const KArgs& A, const double* U, double* G, hipStream_t s) {
   constexpr int EPW = 64 >> (2 * DIM);
   const long long blocks = (A.E + EPW - 1) / EPW;
+  TimedLaunch t(DG2P_K_INGREDIENTS, s);
   hipLaunchKernelGGL((k_face_ingredients<DIM, VISC>), dim3((unsigned)blocks), dim3(64), 0, s, A, U, G);
 }
 
@@ -179,6 +206,7 @@ void launch_stage(int mode, const KArgs& A, const double* Us, const double* G, c
   constexpr int EPW = 64 >> (2 * DIM);
   const long long blocks = (A.E + EPW - 1) / EPW;
   const dim3 g((unsigned)blocks), b(64);
+  TimedLaunch t(DG2P_K_STAGE, s);
   if (mode == 0)
     hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, 0>), g, b, 0, s, A, Us, G, Un, Out, dt);
   else if (mode == 1)
@@ -329,6 +357,7 @@ int dg2p_prim_to_cons(dg2p_mesh m, const dg2p_params* p, const double* prim, dou
   const long long n = m->E * m->nn;
   const unsigned blocks = (unsigned)((n + 255) / 256);
   hipStream_t s = (hipStream_t)stream;
+  TimedLaunch t(DG2P_K_PRIM, s);
   switch (m->dim) {
     case 1: hipLaunchKernelGGL((k_prim_to_cons<1>), dim3(blocks), dim3(256), 0, s, A, prim, U, n); break;
     case 2: hipLaunchKernelGGL((k_prim_to_cons<2>), dim3(blocks), dim3(256), 0, s, A, prim, U, n); break;
@@ -364,6 +393,8 @@ int dg2p_max_dt(dg2p_mesh m, const dg2p_params* p, const double* U, double cfl, 
   const int nb = red_blocks(m);
   hipStream_t s = (hipStream_t)stream;
   const bool v = viscous(p);
+  {
+  TimedLaunch t(DG2P_K_RATE, s);
   switch (m->dim) {
     case 1:
       if (v) hipLaunchKernelGGL((k_rate_partial<1, true>), dim3(nb), dim3(RED_THREADS), 0, s, A, U, part);
@@ -378,8 +409,10 @@ int dg2p_max_dt(dg2p_mesh m, const dg2p_params* p, const double* U, double cfl, 
       else hipLaunchKernelGGL((k_rate_partial<3, false>), dim3(nb), dim3(RED_THREADS), 0, s, A, U, part);
       break;
   }
+  }
   double hmin = m->h[0];
   for (int k = 1; k < m->dim; ++k) hmin = std::fmin(hmin, m->h[k]);
+  TimedLaunch t(DG2P_K_RATE_FINAL, s);
   hipLaunchKernelGGL(k_rate_final, dim3(1), dim3(RED_THREADS), 0, s, part, nb, A.GammaEps, m->dim, hmin,
                      cfl, dt, mon);
   return hip_check(hipGetLastError(), "max_dt launch");
@@ -427,6 +460,8 @@ int dg2p_compute_monitors(dg2p_mesh m, const dg2p_params* p, const double* U, do
   double* part = static_cast<double*>(work);
   const int nb = red_blocks(m);
   hipStream_t s = (hipStream_t)stream;
+  {
+  TimedLaunch t(DG2P_K_MONITOR, s);
   switch (m->dim) {
     case 1:
       hipLaunchKernelGGL((k_monitor_partial<1>), dim3(nb), dim3(RED_THREADS), 0, s, A, U, p_ref, ur[0], ur[1], ur[2], part);
@@ -441,10 +476,43 @@ int dg2p_compute_monitors(dg2p_mesh m, const dg2p_params* p, const double* U, do
       hipLaunchKernelGGL((k_monitor_final<3>), dim3(1), dim3(64), 0, s, part, nb, mon);
       break;
   }
+  }
   st = hip_check(hipGetLastError(), "monitor launch");
   if (st) return st;
   // max_rate is part of the monitor record: reuse the rate reduction (writes mon->max_rate / mon->dt)
   return dg2p_max_dt(m, p, U, 0.1, nullptr, mon, static_cast<char*>(work), stream);
+}
+
+int dg2p_timing_enable(int on) {
+  if (on && !g_timing.created) {
+    for (int i = 0; i < TIMING_SLOTS; ++i) {
+      if (hipEventCreate(&g_timing.start[i]) != hipSuccess || hipEventCreate(&g_timing.stop[i]) != hipSuccess)
+        return fail(DG2P_EHIP, "hipEventCreate failed");
+    }
+    g_timing.created = true;
+  }
+  g_timing.on = on != 0;
+  if (on) g_timing.used = 0;
+  return DG2P_OK;
+}
+
+int dg2p_timing_read(int kernel, double* mean_ms, long long* count) {
+  if (!mean_ms || !count) return fail(DG2P_EINVAL, "mean_ms and count must be non-NULL");
+  double sum = 0.0;
+  long long n = 0;
+  for (int i = 0; i < g_timing.used; ++i) {
+    if (g_timing.kind[i] != kernel) continue;
+    int st = hip_check(hipEventSynchronize(g_timing.stop[i]), "hipEventSynchronize");
+    if (st) return st;
+    float ms = 0.0f;
+    st = hip_check(hipEventElapsedTime(&ms, g_timing.start[i], g_timing.stop[i]), "hipEventElapsedTime");
+    if (st) return st;
+    sum += ms;
+    ++n;
+  }
+  *mean_ms = n ? sum / (double)n : 0.0;
+  *count = n;
+  return DG2P_OK;
 }
 
 }  // extern "C"

@@ -68,7 +68,10 @@ _SIG = {
     "dg2p_max_dt": ([_vp, ctypes.POINTER(Params), _dp, _d, _dp, _vp, _vp, _vp], _i),
     "dg2p_rk_step": ([_vp, ctypes.POINTER(Params), _dp, _dp, _vp, _vp], _i),
     "dg2p_compute_monitors": ([_vp, ctypes.POINTER(Params), _dp, _d, _dp, _vp, _vp, _vp], _i),
+    "dg2p_timing_enable": ([_i], _i),
+    "dg2p_timing_read": ([_i, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_longlong)], _i),
 }
+K_INGREDIENTS, K_STAGE, K_RATE, K_RATE_FINAL, K_MONITOR, K_PRIM = range(6)
 for _name, (_args, _res) in _SIG.items():
     _fn = getattr(_lib, _name)
     _fn.argtypes = _args
@@ -246,6 +249,18 @@ def monitors(mesh, params, U, p_ref=0.0, u_ref=None, stream=None, sync=True):
     return dict(max_rate=m.max_rate, dt=m.dt, min_alpha=m.min_alpha, max_alpha=m.max_alpha,
                 integral=list(m.integral)[:mesh.nf], dev_p=m.dev_p, dev_u=m.dev_u,
                 nonphys=int(m.nonphys))
+
+
+def timing_enable(on=True):
+    """Bracket every library kernel launch with hipEvents (benchmarks only)."""
+    _check(_lib.dg2p_timing_enable(1 if on else 0), "dg2p_timing_enable")
+
+
+def timing_read(kind):
+    """(mean ms, count) of the recorded launches of one kernel kind."""
+    ms, n = ctypes.c_double(), ctypes.c_longlong()
+    _check(_lib.dg2p_timing_read(kind, ctypes.byref(ms), ctypes.byref(n)), "dg2p_timing_read")
+    return ms.value, n.value
 
 
 def mesh_from_config(cfg, params=None):

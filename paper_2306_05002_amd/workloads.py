@@ -112,17 +112,23 @@ def config(name, n_elem=None):
 def _rt_interface_noise(x, y):
     """Seeded 1e-3 perturbation of the Rayleigh-Taylor interface: 4 x 4 Fourier
     modes with N(0,1) amplitudes (seed 3), scaled to max |zeta| = 1 on a 256^2
-    grid."""
+    grid.  Separable form: cos/sin of 2 pi (m x + n y) from the per-axis
+    harmonics (8 transcendental evaluations per axis instead of 32 per point)."""
     rng = np.random.default_rng(3)
     A = rng.standard_normal((4, 4))
     B = rng.standard_normal((4, 4))
 
     def zeta(xx, yy):
-        z = np.zeros_like(xx)
-        for m in range(1, 5):
-            for n in range(1, 5):
-                arg = 2.0 * math.pi * (m * xx + n * yy)
-                z += A[m - 1, n - 1] * np.cos(arg) + B[m - 1, n - 1] * np.sin(arg)
+        cx = [np.cos(2.0 * math.pi * m * xx) for m in range(1, 5)]
+        sx = [np.sin(2.0 * math.pi * m * xx) for m in range(1, 5)]
+        cy = [np.cos(2.0 * math.pi * n * yy) for n in range(1, 5)]
+        sy = [np.sin(2.0 * math.pi * n * yy) for n in range(1, 5)]
+        z = np.zeros(np.broadcast(xx, yy).shape)
+        for m in range(4):
+            for n in range(4):
+                c = cx[m] * cy[n] - sx[m] * sy[n]      # cos 2 pi (m x + n y)
+                s_ = sx[m] * cy[n] + cx[m] * sy[n]     # sin 2 pi (m x + n y)
+                z += A[m, n] * c + B[m, n] * s_
         return z
 
     g = (np.arange(256) + 0.5) / 256.0
