@@ -81,7 +81,8 @@ typedef enum {
   DG2P_OP_MAX_DT = 2,
   DG2P_OP_MONITORS = 3,
   DG2P_OP_RHS_VJP = 4,
-  DG2P_OP_RK_STEP_VJP = 5
+  DG2P_OP_RK_STEP_VJP = 5,
+  DG2P_OP_ADVANCE = 6
 } dg2p_op;
 
 /* Structured Cartesian grid of dim-dimensional tensor-product elements
@@ -172,6 +173,19 @@ int dg2p_max_dt(dg2p_mesh m, const dg2p_params* p /*host*/, const double* U /*de
  * dt: device scalar (no host synchronisation).  work: DG2P_OP_RK_STEP bytes. */
 int dg2p_rk_step(dg2p_mesh m, const dg2p_params* p /*host*/, double* U /*device, in/out*/,
                  const double* dt /*device*/, void* work /*device*/, void* stream);
+
+/* Advance U in place by n_steps SSP-RK3 steps without host synchronisation.
+ * Each step's dt is cfl / max_rate of the step's initial state (the rule of
+ * dg2p_max_dt), reduced on the device, or *dt_fixed when dt_fixed != NULL
+ * (device scalar; a frozen schedule).  Optional device outputs: *t is
+ * incremented by every dt taken, *dt_last receives the last dt, *mon the
+ * monitors of the final state (p_ref, u_ref as in dg2p_compute_monitors).
+ * Produces the same states as n_steps calls of dg2p_rk_step with those dt.
+ * work: dg2p_workspace_size(DG2P_OP_ADVANCE) bytes. */
+int dg2p_advance(dg2p_mesh m, const dg2p_params* p /*host*/, double* U /*device, in/out*/, int n_steps,
+                 double cfl, const double* dt_fixed /*device, nullable*/, double* t /*device, nullable*/,
+                 double* dt_last /*device, nullable*/, dg2p_monitors* mon /*device, nullable*/,
+                 double p_ref, const double* u_ref /*host, nullable*/, void* work /*device*/, void* stream);
 
 /* Monitors of a state (all fields of *mon; dt is set to 0.1 / max_rate).  p_ref and u_ref are
  * the reference pressure and velocity of dev_p / dev_u (host values).

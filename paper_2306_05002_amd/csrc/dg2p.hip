@@ -87,12 +87,14 @@ int check_params(const dg2p_mesh_s* m, const dg2p_params* p) {
   return DG2P_OK;
 }
 
-bool viscous(const dg2p_params* p) { return p->mu[0] != 0.0 || p->mu[1] != 0.0; }
 
 KArgs make_args(const dg2p_mesh_s* m, const dg2p_params* p) {
   KArgs A;
   std::memset(&A, 0, sizeof(A));
   A.E = m->E;
+  const int epw = 64 >> (2 * m->dim);
+  A.nblocks = (m->E + (long long)(BLOCK / 64) * epw - 1) / ((long long)(BLOCK / 64) * epw);
+  A.xcd_chunk = (A.nblocks + 7) / 8;
   for (int k = 0; k < 3; ++k) {
     A.N[k] = k < m->dim ? m->N[k] : 1;
     for (int s = 0; s < 2; ++s) {
@@ -104,14 +106,9 @@ KArgs make_args(const dg2p_mesh_s* m, const dg2p_params* p) {
     A.Jinv[k] = 1.0 / J;
     A.lift[k] = 1.0 / (m->w[0] * J);
     A.pen[k] = p->c_ip * 16.0 / h;
-    for (int a = 0; a < 4; ++a) {
-      A.symw[k][0][a] = m->D[0][a] / (2.0 * m->w[a] * J * J);
-      A.symw[k][1][a] = m->D[3][a] / (2.0 * m->w[a] * J * J);
-      A.wJ[k][a] = m->w[a] * J;
-    }
+    A.J[k] = J;
+    A.hJ2inv[k] = 1.0 / (2.0 * J * J);
   }
-  for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b) A.D[a][b] = m->D[a][b];
   const double g1 = p->gamma[0], g2 = p->gamma[1];
   A.xi1 = 1.0 / (g1 - 1.0);
   A.xi2 = 1.0 / (g2 - 1.0);
@@ -168,6 +165,14 @@ struct TimedLaunch {
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+bool viscous(const dg2p_params* p) { return p->mu[0] != 0.0 || p->mu[1] != 0.0; }
+bool has_dirichlet(const dg2p_mesh_s* m) {
+  for (int k = 0; k < m->dim; ++k)
+    for (int s = 0; s < 2; ++s)
+      if (m->desc.bc[k][s] == DG2P_BC_DIRICHLET) return true;
+  return false;
+}
+
 size_t g_bytes(const dg2p_mesh_s* m, const dg2p_params* p) {
   const int C = viscous(p) ? 1 + m->dim : 1;
   return align256(sizeof(double) * (size_t)(2 * m->dim) * C * (size_t)m->E * m->nfn);
@@ -175,14 +180,62 @@ size_t g_bytes(const dg2p_mesh_s* m, const dg2p_params* p) {
 size_t state_bytes(const dg2p_mesh_s* m) {
   return align256(sizeof(double) * (size_t)m->nf * (size_t)m->E * m->nn);
 }
-size_t red_bytes() { return align256(sizeof(double) * (size_t)RED_BLOCKS * MON_SLOTS); }
+constexpr long long REC2_MAX = 1024;   // second-level records
+constexpr long long REC_GRID = 1024;   // workgroups of the stand-alone record pass
+long long elem_blocks(const dg2p_mesh_s* m) {
+  const long long per = (long long)(BLOCK / 64) * (64 >> (2 * m->dim));
+  return (m->E + per - 1) / per;
+}
+size_t rec_bytes(const dg2p_mesh_s* m) {
+  long long n = elem_blocks(m);
+  if (n < REC_GRID) n = REC_GRID;
+  return align256(sizeof(double) * (size_t)REC * (size_t)(n + REC2_MAX)) + 256;
+}
 
-int red_blocks(const dg2p_mesh_s* m) {
-  const long long n = m->E * m->nn;
-  long long b = (n + RED_THREADS - 1) / RED_THREADS;
-  if (b > RED_BLOCKS) b = RED_BLOCKS;
-  if (b < 1) b = 1;
-  return (int)b;
+struct Work {
+  double* G0 = nullptr;
+  double* G1 = nullptr;
+  double* U1 = nullptr;
+  double* U2 = nullptr;
+  double* rec = nullptr;
+  double* rec2 = nullptr;
+  double* dt = nullptr;  // internal device scalar
+};
+
+size_t work_bytes(const dg2p_mesh_s* m, const dg2p_params* p, int op) {
+  switch (op) {
+    case DG2P_OP_RHS: return g_bytes(m, p) + rec_bytes(m);
+    case DG2P_OP_RK_STEP: return 2 * g_bytes(m, p) + 2 * state_bytes(m) + rec_bytes(m);
+    case DG2P_OP_ADVANCE: return 2 * g_bytes(m, p) + 2 * state_bytes(m) + rec_bytes(m) + 256;
+    case DG2P_OP_MAX_DT:
+    case DG2P_OP_MONITORS: return rec_bytes(m);
+    default: return 0;
+  }
+}
+
+Work carve(const dg2p_mesh_s* m, const dg2p_params* p, int op, void* work) {
+  Work w;
+  char* c = static_cast<char*>(work);
+  const size_t gb = g_bytes(m, p), sb = state_bytes(m);
+  if (op == DG2P_OP_RHS || op == DG2P_OP_RK_STEP || op == DG2P_OP_ADVANCE) {
+    w.G0 = reinterpret_cast<double*>(c);
+    c += gb;
+  }
+  if (op == DG2P_OP_RK_STEP || op == DG2P_OP_ADVANCE) {
+    w.G1 = reinterpret_cast<double*>(c);
+    c += gb;
+    w.U1 = reinterpret_cast<double*>(c);
+    c += sb;
+    w.U2 = reinterpret_cast<double*>(c);
+    c += sb;
+  }
+  w.rec = reinterpret_cast<double*>(c);
+  long long n = elem_blocks(m);
+  if (n < REC_GRID) n = REC_GRID;
+  w.rec2 = w.rec + (size_t)REC * n;
+  c += rec_bytes(m);
+  if (op == DG2P_OP_ADVANCE) w.dt = reinterpret_cast<double*>(c);
+  return w;
 }
 
 int check_ws(void* work, size_t need) {
@@ -192,57 +245,113 @@ int check_ws(void* work, size_t need) {
   return DG2P_OK;
 }
 
+dim3 elem_grid(const KArgs& A) { return dim3((unsigned)(8 * A.xcd_chunk)); }
+
 template <int DIM, bool VISC>
-void launch_ingredients(const KArgs& A, const double* U, double* G, hipStream_t s) {
-  constexpr int EPW = 64 >> (2 * DIM);
-  const long long blocks = (A.E + EPW - 1) / EPW;
+void launch_ingredients(const KArgs& A, const double* U, double* G, double* rec, hipStream_t s) {
   TimedLaunch t(DG2P_K_INGREDIENTS, s);
-  hipLaunchKernelGGL((k_face_ingredients<DIM, VISC>), dim3((unsigned)blocks), dim3(64), 0, s, A, U, G);
+  hipLaunchKernelGGL((k_ingredients<DIM, VISC>), elem_grid(A), dim3(BLOCK), 0, s, A, U, G, rec);
 }
 
-template <int DIM, bool VISC, bool CSF>
-void launch_stage(int mode, const KArgs& A, const double* Us, const double* G, const double* Un,
-                  double* Out, const double* dt, hipStream_t s) {
-  constexpr int EPW = 64 >> (2 * DIM);
-  const long long blocks = (A.E + EPW - 1) / EPW;
-  const dim3 g((unsigned)blocks), b(64);
+template <int DIM, bool VISC, bool CSF, bool DIRI>
+void launch_stage_t(int mode, int epi, const KArgs& A, const StageIO& io, hipStream_t s) {
   TimedLaunch t(DG2P_K_STAGE, s);
+  const dim3 g = elem_grid(A), b(BLOCK);
   if (mode == 0)
-    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, 0>), g, b, 0, s, A, Us, G, Un, Out, dt);
+    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 0, 0>), g, b, 0, s, A, io);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, 1>), g, b, 0, s, A, Us, G, Un, Out, dt);
+    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 1, 1>), g, b, 0, s, A, io);
+  else if (epi == 1)
+    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 2, 1>), g, b, 0, s, A, io);
+  else if (epi == 2)
+    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 2, 2>), g, b, 0, s, A, io);
   else
-    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, 2>), g, b, 0, s, A, Us, G, Un, Out, dt);
+    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 2, 0>), g, b, 0, s, A, io);
 }
 
 template <int DIM>
-int residual_pass(int mode, const dg2p_mesh_s* m, const dg2p_params* p, KArgs& A, const double* Us,
-                  double* G, const double* Un, double* Out, const double* dt, hipStream_t s) {
-  const bool visc = viscous(p);
-  const bool csf = p->sigma != 0.0;
-  if (visc)
-    launch_ingredients<DIM, true>(A, Us, G, s);
-  else
-    launch_ingredients<DIM, false>(A, Us, G, s);
-  if (visc && csf)
-    launch_stage<DIM, true, true>(mode, A, Us, G, Un, Out, dt, s);
-  else if (visc)
-    launch_stage<DIM, true, false>(mode, A, Us, G, Un, Out, dt, s);
-  else if (csf)
-    launch_stage<DIM, false, true>(mode, A, Us, G, Un, Out, dt, s);
-  else
-    launch_stage<DIM, false, false>(mode, A, Us, G, Un, Out, dt, s);
-  (void)m;
-  return hip_check(hipGetLastError(), "stage launch");
+void launch_stage_d(const dg2p_mesh_s* m, const dg2p_params* p, int mode, int epi, const KArgs& A,
+                    const StageIO& io, hipStream_t s) {
+  const bool visc = viscous(p), csf = p->sigma != 0.0, diri = has_dirichlet(m);
+  if (diri) {
+    if (visc && csf) launch_stage_t<DIM, true, true, true>(mode, epi, A, io, s);
+    else if (visc) launch_stage_t<DIM, true, false, true>(mode, epi, A, io, s);
+    else if (csf) launch_stage_t<DIM, false, true, true>(mode, epi, A, io, s);
+    else launch_stage_t<DIM, false, false, true>(mode, epi, A, io, s);
+  } else {
+    if (visc && csf) launch_stage_t<DIM, true, true, false>(mode, epi, A, io, s);
+    else if (visc) launch_stage_t<DIM, true, false, false>(mode, epi, A, io, s);
+    else if (csf) launch_stage_t<DIM, false, true, false>(mode, epi, A, io, s);
+    else launch_stage_t<DIM, false, false, false>(mode, epi, A, io, s);
+  }
 }
 
-int residual(int mode, const dg2p_mesh_s* m, const dg2p_params* p, KArgs& A, const double* Us,
-             double* G, const double* Un, double* Out, const double* dt, hipStream_t s) {
+void launch_stage(const dg2p_mesh_s* m, const dg2p_params* p, int mode, int epi, const KArgs& A,
+                  const StageIO& io, hipStream_t s) {
   switch (m->dim) {
-    case 1: return residual_pass<1>(mode, m, p, A, Us, G, Un, Out, dt, s);
-    case 2: return residual_pass<2>(mode, m, p, A, Us, G, Un, Out, dt, s);
-    default: return residual_pass<3>(mode, m, p, A, Us, G, Un, Out, dt, s);
+    case 1: launch_stage_d<1>(m, p, mode, epi, A, io, s); break;
+    case 2: launch_stage_d<2>(m, p, mode, epi, A, io, s); break;
+    default: launch_stage_d<3>(m, p, mode, epi, A, io, s); break;
   }
+}
+
+void launch_ingr(const dg2p_mesh_s* m, const dg2p_params* p, const KArgs& A, const double* U, double* G,
+                 double* rec, hipStream_t s) {
+  const bool v = viscous(p);
+  switch (m->dim) {
+    case 1: v ? launch_ingredients<1, true>(A, U, G, rec, s) : launch_ingredients<1, false>(A, U, G, rec, s); break;
+    case 2: v ? launch_ingredients<2, true>(A, U, G, rec, s) : launch_ingredients<2, false>(A, U, G, rec, s); break;
+    default: v ? launch_ingredients<3, true>(A, U, G, rec, s) : launch_ingredients<3, false>(A, U, G, rec, s); break;
+  }
+}
+
+void launch_records(const dg2p_mesh_s* m, const dg2p_params* p, const KArgs& A, const double* U, double* rec,
+                    hipStream_t s) {
+  TimedLaunch t(DG2P_K_RATE, s);
+  const bool v = viscous(p);
+  long long n = m->E * m->nn;
+  long long gb = (n + BLOCK - 1) / BLOCK;
+  if (gb > REC_GRID) gb = REC_GRID;
+  const dim3 g((unsigned)gb), b(BLOCK);
+  if (m->dim == 1) {
+    if (v) hipLaunchKernelGGL((k_records<1, true>), g, b, 0, s, A, U, rec);
+    else hipLaunchKernelGGL((k_records<1, false>), g, b, 0, s, A, U, rec);
+  } else if (m->dim == 2) {
+    if (v) hipLaunchKernelGGL((k_records<2, true>), g, b, 0, s, A, U, rec);
+    else hipLaunchKernelGGL((k_records<2, false>), g, b, 0, s, A, U, rec);
+  } else {
+    if (v) hipLaunchKernelGGL((k_records<3, true>), g, b, 0, s, A, U, rec);
+    else hipLaunchKernelGGL((k_records<3, false>), g, b, 0, s, A, U, rec);
+  }
+}
+
+long long records_of_records(const dg2p_mesh_s* m, const dg2p_params* p, int standalone) {
+  (void)p;
+  if (standalone) {
+    long long n = m->E * m->nn;
+    long long gb = (n + BLOCK - 1) / BLOCK;
+    return gb > REC_GRID ? REC_GRID : gb;
+  }
+  return elem_blocks(m);
+}
+
+// Reduce n records to dt / monitors (two levels when n is large).
+void finalize(const dg2p_mesh_s* m, const KArgs& A, const Work& w, long long n, double cfl, const double* dt_fixed,
+              double* dt, double* t, dg2p_monitors* mon, hipStream_t s) {
+  TimedLaunch tl(DG2P_K_RATE_FINAL, s);
+  const double* src = w.rec;
+  if (n > 4 * BLOCK) {
+    long long chunk = (n + REC2_MAX - 1) / REC2_MAX;
+    if (chunk < BLOCK) chunk = BLOCK;
+    const long long nb = (n + chunk - 1) / chunk;
+    hipLaunchKernelGGL(k_reduce_records, dim3((unsigned)nb), dim3(BLOCK), 0, s, w.rec, n, chunk, w.rec2);
+    src = w.rec2;
+    n = nb;
+  }
+  double hmin = m->h[0];
+  for (int k = 1; k < m->dim; ++k) hmin = std::fmin(hmin, m->h[k]);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLOCK), 0, s, src, n, A.GammaEps, m->dim, m->nf, hmin, cfl,
+                     dt_fixed, dt, t, mon);
 }
 
 }  // namespace
@@ -339,10 +448,11 @@ int dg2p_workspace_size(dg2p_mesh m, const dg2p_params* p, int op, size_t* bytes
   int st = check_params(m, p);
   if (st) return st;
   switch (op) {
-    case DG2P_OP_RHS: *bytes = g_bytes(m, p); break;
-    case DG2P_OP_RK_STEP: *bytes = g_bytes(m, p) + 2 * state_bytes(m); break;
+    case DG2P_OP_RHS:
+    case DG2P_OP_RK_STEP:
+    case DG2P_OP_ADVANCE:
     case DG2P_OP_MAX_DT:
-    case DG2P_OP_MONITORS: *bytes = red_bytes(); break;
+    case DG2P_OP_MONITORS: *bytes = work_bytes(m, p, op); break;
     default: return fail(DG2P_EUNSUPPORTED, "operation not available in this build");
   }
   return DG2P_OK;
@@ -351,6 +461,7 @@ int dg2p_workspace_size(dg2p_mesh m, const dg2p_params* p, int op, size_t* bytes
 int dg2p_prim_to_cons(dg2p_mesh m, const dg2p_params* p, const double* prim, double* U, void* stream) {
   g_last_error.clear();
   if (!m || !prim || !U) return fail(DG2P_EINVAL, "mesh, prim and U must be non-NULL");
+  if (prim == U) return fail(DG2P_EINVAL, "prim and U may not alias");
   int st = check_params(m, p);
   if (st) return st;
   KArgs A = make_args(m, p);
@@ -372,11 +483,15 @@ int dg2p_rhs(dg2p_mesh m, const dg2p_params* p, const double* U, double* R, void
   if (U == R) return fail(DG2P_EINVAL, "U and R may not alias");
   int st = check_params(m, p);
   if (st) return st;
-  st = check_ws(work, g_bytes(m, p));
+  st = check_ws(work, work_bytes(m, p, DG2P_OP_RHS));
   if (st) return st;
   KArgs A = make_args(m, p);
-  double* G = static_cast<double*>(work);
-  return residual(0, m, p, A, U, G, nullptr, R, nullptr, (hipStream_t)stream);
+  Work w = carve(m, p, DG2P_OP_RHS, work);
+  hipStream_t s = (hipStream_t)stream;
+  launch_ingr(m, p, A, U, w.G0, w.rec, s);
+  StageIO io{U, w.G0, nullptr, R, nullptr, nullptr, nullptr};
+  launch_stage(m, p, 0, 0, A, io, s);
+  return hip_check(hipGetLastError(), "rhs launch");
 }
 
 int dg2p_max_dt(dg2p_mesh m, const dg2p_params* p, const double* U, double cfl, double* dt,
@@ -386,35 +501,13 @@ int dg2p_max_dt(dg2p_mesh m, const dg2p_params* p, const double* U, double cfl, 
   if (!(cfl > 0.0)) return fail(DG2P_EINVAL, "cfl must be > 0");
   int st = check_params(m, p);
   if (st) return st;
-  st = check_ws(work, red_bytes());
+  st = check_ws(work, work_bytes(m, p, DG2P_OP_MAX_DT));
   if (st) return st;
   KArgs A = make_args(m, p);
-  double* part = static_cast<double*>(work);
-  const int nb = red_blocks(m);
+  Work w = carve(m, p, DG2P_OP_MAX_DT, work);
   hipStream_t s = (hipStream_t)stream;
-  const bool v = viscous(p);
-  {
-  TimedLaunch t(DG2P_K_RATE, s);
-  switch (m->dim) {
-    case 1:
-      if (v) hipLaunchKernelGGL((k_rate_partial<1, true>), dim3(nb), dim3(RED_THREADS), 0, s, A, U, part);
-      else hipLaunchKernelGGL((k_rate_partial<1, false>), dim3(nb), dim3(RED_THREADS), 0, s, A, U, part);
-      break;
-    case 2:
-      if (v) hipLaunchKernelGGL((k_rate_partial<2, true>), dim3(nb), dim3(RED_THREADS), 0, s, A, U, part);
-      else hipLaunchKernelGGL((k_rate_partial<2, false>), dim3(nb), dim3(RED_THREADS), 0, s, A, U, part);
-      break;
-    default:
-      if (v) hipLaunchKernelGGL((k_rate_partial<3, true>), dim3(nb), dim3(RED_THREADS), 0, s, A, U, part);
-      else hipLaunchKernelGGL((k_rate_partial<3, false>), dim3(nb), dim3(RED_THREADS), 0, s, A, U, part);
-      break;
-  }
-  }
-  double hmin = m->h[0];
-  for (int k = 1; k < m->dim; ++k) hmin = std::fmin(hmin, m->h[k]);
-  TimedLaunch t(DG2P_K_RATE_FINAL, s);
-  hipLaunchKernelGGL(k_rate_final, dim3(1), dim3(RED_THREADS), 0, s, part, nb, A.GammaEps, m->dim, hmin,
-                     cfl, dt, mon);
+  launch_records(m, p, A, U, w.rec, s);
+  finalize(m, A, w, records_of_records(m, p, 1), cfl, nullptr, dt, nullptr, mon, s);
   return hip_check(hipGetLastError(), "max_dt launch");
 }
 
@@ -423,64 +516,88 @@ int dg2p_rk_step(dg2p_mesh m, const dg2p_params* p, double* U, const double* dt,
   if (!m || !U || !dt) return fail(DG2P_EINVAL, "mesh, U and dt must be non-NULL");
   int st = check_params(m, p);
   if (st) return st;
-  st = check_ws(work, g_bytes(m, p) + 2 * state_bytes(m));
+  st = check_ws(work, work_bytes(m, p, DG2P_OP_RK_STEP));
   if (st) return st;
   KArgs A = make_args(m, p);
-  char* w = static_cast<char*>(work);
-  double* G = reinterpret_cast<double*>(w);
-  double* U1 = reinterpret_cast<double*>(w + g_bytes(m, p));
-  double* U2 = reinterpret_cast<double*>(w + g_bytes(m, p) + state_bytes(m));
+  Work w = carve(m, p, DG2P_OP_RK_STEP, work);
   hipStream_t s = (hipStream_t)stream;
+  launch_ingr(m, p, A, U, w.G0, w.rec, s);
   // stage 1: U1 = U + dt R(U)
-  st = residual(1, m, p, A, U, G, nullptr, U1, dt, s);
-  if (st) return st;
+  StageIO io1{U, w.G0, nullptr, w.U1, w.G1, w.rec, dt};
+  launch_stage(m, p, 1, 1, A, io1, s);
   // stage 2: U2 = 3/4 U + 1/4 (U1 + dt R(U1))
   A.rk_a = 0.75;
   A.rk_b = 0.25;
-  st = residual(2, m, p, A, U1, G, U, U2, dt, s);
-  if (st) return st;
+  StageIO io2{w.U1, w.G1, U, w.U2, w.G0, w.rec, dt};
+  launch_stage(m, p, 2, 1, A, io2, s);
   // stage 3: U <- 1/3 U + 2/3 (U2 + dt R(U2)); each node reads its own U before writing it
   A.rk_a = 1.0 / 3.0;
   A.rk_b = 2.0 / 3.0;
-  return residual(2, m, p, A, U2, G, U, U, dt, s);
+  StageIO io3{w.U2, w.G0, U, U, nullptr, nullptr, dt};
+  launch_stage(m, p, 2, 0, A, io3, s);
+  return hip_check(hipGetLastError(), "rk_step launch");
+}
+
+int dg2p_advance(dg2p_mesh m, const dg2p_params* p, double* U, int n_steps, double cfl, const double* dt_fixed,
+                 double* t, double* dt_last, dg2p_monitors* mon, double p_ref, const double* u_ref, void* work,
+                 void* stream) {
+  g_last_error.clear();
+  if (!m || !U) return fail(DG2P_EINVAL, "mesh and U must be non-NULL");
+  if (n_steps < 0) return fail(DG2P_EINVAL, "n_steps must be >= 0");
+  if (!dt_fixed && !(cfl > 0.0)) return fail(DG2P_EINVAL, "cfl must be > 0");
+  int st = check_params(m, p);
+  if (st) return st;
+  st = check_ws(work, work_bytes(m, p, DG2P_OP_ADVANCE));
+  if (st) return st;
+  KArgs A = make_args(m, p);
+  A.p_ref = p_ref;
+  if (u_ref)
+    for (int k = 0; k < m->dim; ++k) A.u_ref[k] = u_ref[k];
+  Work w = carve(m, p, DG2P_OP_ADVANCE, work);
+  hipStream_t s = (hipStream_t)stream;
+  double* dts = dt_last ? dt_last : w.dt;
+  double* Ga = w.G0;
+  double* Gb = w.G1;
+  const long long nrec = records_of_records(m, p, 0);
+  launch_ingr(m, p, A, U, Ga, w.rec, s);
+  for (int it = 0; it < n_steps; ++it) {
+    finalize(m, A, w, nrec, cfl, dt_fixed, dts, t, nullptr, s);
+    KArgs B = A;
+    StageIO io1{U, Ga, nullptr, w.U1, Gb, nullptr, dts};
+    launch_stage(m, p, 1, 1, B, io1, s);
+    B.rk_a = 0.75;
+    B.rk_b = 0.25;
+    StageIO io2{w.U1, Gb, U, w.U2, Ga, nullptr, dts};
+    launch_stage(m, p, 2, 1, B, io2, s);
+    B.rk_a = 1.0 / 3.0;
+    B.rk_b = 2.0 / 3.0;
+    StageIO io3{w.U2, Ga, U, U, Gb, w.rec, dts};
+    launch_stage(m, p, 2, 2, B, io3, s);
+    double* tmp = Ga;
+    Ga = Gb;
+    Gb = tmp;
+  }
+  if (mon) finalize(m, A, w, nrec, cfl, nullptr, nullptr, nullptr, mon, s);
+  return hip_check(hipGetLastError(), "advance launch");
 }
 
 int dg2p_compute_monitors(dg2p_mesh m, const dg2p_params* p, const double* U, double p_ref, const double* u_ref,
-                  dg2p_monitors* mon, void* work, void* stream) {
+                          dg2p_monitors* mon, void* work, void* stream) {
   g_last_error.clear();
   if (!m || !U || !mon) return fail(DG2P_EINVAL, "mesh, U and mon must be non-NULL");
   int st = check_params(m, p);
   if (st) return st;
-  st = check_ws(work, red_bytes());
+  st = check_ws(work, work_bytes(m, p, DG2P_OP_MONITORS));
   if (st) return st;
   KArgs A = make_args(m, p);
-  double ur[3] = {0.0, 0.0, 0.0};
+  A.p_ref = p_ref;
   if (u_ref)
-    for (int k = 0; k < m->dim; ++k) ur[k] = u_ref[k];
-  double* part = static_cast<double*>(work);
-  const int nb = red_blocks(m);
+    for (int k = 0; k < m->dim; ++k) A.u_ref[k] = u_ref[k];
+  Work w = carve(m, p, DG2P_OP_MONITORS, work);
   hipStream_t s = (hipStream_t)stream;
-  {
-  TimedLaunch t(DG2P_K_MONITOR, s);
-  switch (m->dim) {
-    case 1:
-      hipLaunchKernelGGL((k_monitor_partial<1>), dim3(nb), dim3(RED_THREADS), 0, s, A, U, p_ref, ur[0], ur[1], ur[2], part);
-      hipLaunchKernelGGL((k_monitor_final<1>), dim3(1), dim3(64), 0, s, part, nb, mon);
-      break;
-    case 2:
-      hipLaunchKernelGGL((k_monitor_partial<2>), dim3(nb), dim3(RED_THREADS), 0, s, A, U, p_ref, ur[0], ur[1], ur[2], part);
-      hipLaunchKernelGGL((k_monitor_final<2>), dim3(1), dim3(64), 0, s, part, nb, mon);
-      break;
-    default:
-      hipLaunchKernelGGL((k_monitor_partial<3>), dim3(nb), dim3(RED_THREADS), 0, s, A, U, p_ref, ur[0], ur[1], ur[2], part);
-      hipLaunchKernelGGL((k_monitor_final<3>), dim3(1), dim3(64), 0, s, part, nb, mon);
-      break;
-  }
-  }
-  st = hip_check(hipGetLastError(), "monitor launch");
-  if (st) return st;
-  // max_rate is part of the monitor record: reuse the rate reduction (writes mon->max_rate / mon->dt)
-  return dg2p_max_dt(m, p, U, 0.1, nullptr, mon, static_cast<char*>(work), stream);
+  launch_records(m, p, A, U, w.rec, s);
+  finalize(m, A, w, records_of_records(m, p, 1), 0.1, nullptr, nullptr, nullptr, mon, s);
+  return hip_check(hipGetLastError(), "monitor launch");
 }
 
 int dg2p_timing_enable(int on) {

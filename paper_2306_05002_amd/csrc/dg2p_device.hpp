@@ -2,20 +2,32 @@
 //
 // Mapping: one lane per GLL node.  An element of 4^d nodes occupies 4^d
 // consecutive lanes (1D: 4 lanes, 16 elements per wave; 2D: 16 lanes, 4
-// elements per wave; 3D: the whole 64-lane wave), so a wave-wide load of one
-// field of U[f][e][j] is 512 contiguous bytes.  The lane index inside an
-// element is the node index j = a_x + 4 a_y + 16 a_z, so the nodes of a line
-// along axis k sit at lane stride 4^k, and the 4-point derivative contraction
-// along k is a cross-lane gather inside the wave (no LDS round trip).
+// elements per wave; 3D: the whole wave), so a wave-wide load of one field
+// of U[f][e][j] is 512 contiguous bytes.  The lane index inside an element is
+// the node index j = a_x + 4 a_y + 16 a_z: the nodes of an x-line form a quad
+// of lanes, those of a y-line sit at stride 4 inside a 16-lane row and those
+// of a z-line at stride 16.  The 4-point derivative contraction along x uses
+// DPP quad rotations, along y DPP row rotations (both plain VALU moves, no LDS
+// traffic) and along z cross-row lane swaps; the per-lane coefficients are the
+// rows of D rotated to match the lane each moved value comes from.
+//
+// Workgroups are 4 independent waves (256 threads).  Consecutive workgroups
+// are dispatched round-robin over the 8 XCDs; the kernels remap the
+// workgroup index so that each XCD sweeps one contiguous slab of elements,
+// which keeps face neighbours in the same L2.
 //
 // Every element evaluates all of its own faces ("owner computes"): the
 // numerical fluxes are recomputed from both traces by the two elements that
-// share a face, so no face buffer is ever written twice and the result is
+// share a face, so no face value is written twice and results are
 // deterministic without atomics.  The neighbour's normal interface flux
 // a.e_k and viscous traction tau.e_k at its face nodes need its own
-// element-local gradients; they are produced by a separate pass
-// (face-ingredient buffer G) because a neighbour's gradient needs the whole
-// neighbour element.
+// element-local gradients; they come from a face-ingredient buffer G that is
+// written by the epilogue of the pass producing that state (the previous RK
+// stage, or an ingredient pass for the first stage).  The same epilogue emits
+// per-workgroup reduction records (largest wave speed, largest kinematic
+// viscosity, alpha range, non-physical count, field integrals, deviations
+// from reference P and u) from which the next time step and the monitors are
+// reduced in a fixed order.
 
 #pragma once
 
@@ -25,19 +37,68 @@
 
 namespace dg2p {
 
-constexpr int NP = 4;  // GLL nodes per axis (p = 3)
+constexpr int BLOCK = 256;      // threads per workgroup (4 independent waves)
+constexpr int REC = 16;         // doubles per reduction record
+// record slots
+constexpr int R_WAVE = 0, R_NU = 1, R_AMIN = 2, R_AMAX = 3, R_BAD = 4, R_DEVP = 5, R_DEVU = 6,
+              R_INT = 7;        // R_INT .. R_INT+7: field integrals
+
+// ---- GLL tables of degree 3, built at compile time ----------------------------
+// Nodes -1, -1/sqrt(5), 1/sqrt(5), 1; weights 1/6, 5/6, 5/6, 1/6;
+// D[a][b] = l_b'(x_a) from the product rule of the Lagrange basis.
+constexpr double csqrt(double x) {
+  double r = x > 1.0 ? x : 1.0;
+  for (int i = 0; i < 64; ++i) r = 0.5 * (r + x / r);
+  return r;
+}
+constexpr double GLL_S = 1.0 / csqrt(5.0);
+struct GllTab {
+  double x[4], w[4], D[4][4];
+};
+constexpr GllTab make_gll() {
+  GllTab t{};
+  t.x[0] = -1.0;
+  t.x[1] = -GLL_S;
+  t.x[2] = GLL_S;
+  t.x[3] = 1.0;
+  t.w[0] = t.w[3] = 1.0 / 6.0;
+  t.w[1] = t.w[2] = 5.0 / 6.0;
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
+      if (a == b) {
+        double s = 0.0;
+        for (int m = 0; m < 4; ++m)
+          if (m != a) s += 1.0 / (t.x[a] - t.x[m]);
+        t.D[a][b] = s;
+      } else {
+        double num = 1.0, den = 1.0;
+        for (int m = 0; m < 4; ++m) {
+          if (m != b) den *= (t.x[b] - t.x[m]);
+          if (m != a && m != b) num *= (t.x[a] - t.x[m]);
+        }
+        t.D[a][b] = num / den;
+      }
+    }
+  return t;
+}
+constexpr GllTab GLL = make_gll();
+// rotated coefficient tables: x quad rotation r, y row rotation by 4r, z lane xor 16r
+constexpr double CX(int a, int r) { return GLL.D[a][(a + r) & 3]; }
+constexpr double CY(int a, int r) { return GLL.D[a][(a - r) & 3]; }
+constexpr double CZ(int a, int r) { return GLL.D[a][a ^ r]; }
 
 struct KArgs {
   long long E;
+  long long nblocks;    // logical workgroups of the element passes
+  long long xcd_chunk;  // logical workgroups per XCD slab
   int N[3];
   int bc[3][2];
   double bcs[3][2][8];
   double Jinv[3];
   double lift[3];       // 1 / (w_0 J_k): face-to-node lift under GLL collocation
   double pen[3];        // c_ip (p+1)^2 / h_k
-  double D[4][4];       // D[a][b] = l_b'(xi_a)
-  double symw[3][2][4]; // D[end][a] / (2 w_a J_k^2), end = 0 (low side) or 3 (high side)
-  double wJ[3][4];      // w_a J_k (diagonal mass factors)
+  double J[3];          // h_k / 2
+  double hJ2inv[3];     // 1 / (2 J_k^2) (SIPG symmetric term)
   // stiffened-gas closure and mixture rules
   double xi1, xi2;      // 1 / (gamma_l - 1)
   double pi1, pi2;      // gamma_l Pinf_l / (gamma_l - 1)
@@ -51,27 +112,127 @@ struct KArgs {
   int has_grav;
   // stage combination U_out = rk_a U_n + rk_b (U_s + dt R)
   double rk_a, rk_b;
+  // reference values of the monitor deviations
+  double p_ref, u_ref[3];
+};
+
+struct StageIO {
+  const double* Us;   // stage input state
+  const double* Gin;  // face ingredients of Us
+  const double* Un;   // U^n (stage combination)
+  double* Out;        // R or the new stage state
+  double* Gout;       // face ingredients of Out (epilogue)
+  double* rec;        // reduction records (epilogue)
+  const double* dt;   // device time step
 };
 
 struct Prim {
-  double rho, u[3], kin, P, c, rH1, rH2;
+  double rho, u[3], kin, P, c, sE;  // sE = rho1 H1 - rho2 H2
 };
 
 __device__ __forceinline__ double sel4(int a, double c0, double c1, double c2, double c3) {
   return a == 0 ? c0 : (a == 1 ? c1 : (a == 2 ? c2 : c3));
 }
 
-// Stiffened-gas primitive recovery of one node (closure of the five-equation
-// model): P = (rho e - Pi) / xi with the mixture xi = sum alpha_l/(gamma_l-1)
-// and Pi = sum alpha_l gamma_l Pinf_l/(gamma_l-1); frozen mixture sound speed
-// c^2 = ((1+xi) P + Pi) / (xi rho); rho_l H_l = gamma_l (P + Pinf_l)/(gamma_l-1).
+// ---- cross-lane moves of a double -------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+// quad rotation: lane a of a quad receives lane (a + R) & 3
+template <int R>
+__device__ __forceinline__ double qrot(double v) {
+  return dpp64<((0 + R) & 3) | (((1 + R) & 3) << 2) | (((2 + R) & 3) << 4) | (((3 + R) & 3) << 6)>(v);
+}
+// quad broadcast of lane S of each quad
+template <int S>
+__device__ __forceinline__ double qbcast(double v) {
+  return dpp64<S | (S << 2) | (S << 4) | (S << 6)>(v);
+}
+// row rotation: lane i of a 16-lane row receives lane (i - 4N) mod 16
+template <int N>
+__device__ __forceinline__ double rrot(double v) {
+  return dpp64<0x120 + 4 * N>(v);
+}
+
+// Per-lane rotated derivative coefficients for each axis.
+template <int DIM>
+struct LaneD {
+  double c[DIM][4];
+};
+
+template <int DIM>
+__device__ __forceinline__ void lane_coeffs(const KArgs& A, const int* ak, LaneD<DIM>& L) {
+  (void)A;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    L.c[0][r] = sel4(ak[0], CX(0, r), CX(1, r), CX(2, r), CX(3, r));
+    if constexpr (DIM > 1) L.c[1][r] = sel4(ak[1], CY(0, r), CY(1, r), CY(2, r), CY(3, r));
+    if constexpr (DIM > 2) L.c[2][r] = sel4(ak[2], CZ(0, r), CZ(1, r), CZ(2, r), CZ(3, r));
+  }
+}
+
+// Sum over the 4 nodes of the lane's line along axis K of D[a_K][b] f_b.
+template <int K, int DIM>
+__device__ __forceinline__ double contract(double f, const LaneD<DIM>& L) {
+  const double* c = L.c[K];
+  if constexpr (K == 0) {
+    double r = c[0] * f;
+    r = fma(c[1], qrot<1>(f), r);
+    r = fma(c[2], qrot<2>(f), r);
+    return fma(c[3], qrot<3>(f), r);
+  } else if constexpr (K == 1) {
+    double r = c[0] * f;
+    r = fma(c[1], rrot<1>(f), r);
+    r = fma(c[2], rrot<2>(f), r);
+    return fma(c[3], rrot<3>(f), r);
+  } else {
+    double r = c[0] * f;
+    r = fma(c[1], __shfl_xor(f, 16), r);
+    r = fma(c[2], __shfl_xor(f, 32), r);
+    return fma(c[3], __shfl_xor(f, 48), r);
+  }
+}
+
+template <int DIM>
+__device__ __forceinline__ double dk(double f, int k, const LaneD<DIM>& L, const KArgs& A) {
+  if (k == 0) return contract<0, DIM>(f, L) * A.Jinv[0];
+  if constexpr (DIM > 1)
+    if (k == 1) return contract<(DIM > 1 ? 1 : 0), DIM>(f, L) * A.Jinv[1];
+  if constexpr (DIM > 2) return contract<(DIM > 2 ? 2 : 0), DIM>(f, L) * A.Jinv[2];
+  return 0.0;
+}
+
+// Value of f at the low (a_k = 0) / high (a_k = 3) end of the lane's line along k.
+template <int K>
+__device__ __forceinline__ double line_end(double f, int ak_k, bool high) {
+  if constexpr (K == 0) {
+    return high ? qbcast<3>(f) : qbcast<0>(f);
+  } else if constexpr (K == 1) {
+    const int lane = __lane_id();
+    return __shfl(f, lane + ((high ? 3 : 0) - ak_k) * 4);
+  } else {
+    const int lane = __lane_id();
+    return __shfl(f, lane + ((high ? 3 : 0) - ak_k) * 16);
+  }
+}
+
+// ---- closure ---------------------------------------------------------------
+// Stiffened-gas primitive recovery of one node: P = (rho e - Pi) / xi with the
+// mixture xi = sum alpha_l/(gamma_l-1) and Pi = sum alpha_l gamma_l Pinf_l/(gamma_l-1);
+// frozen mixture sound speed c^2 = ((1+xi) P + Pi) / (xi rho);
+// rho_l H_l = gamma_l (P + Pinf_l)/(gamma_l-1).
 template <int DIM>
 __device__ __forceinline__ void closure(const KArgs& A, const double* q, Prim& p) {
   p.rho = q[0] + q[1];
+  const double ri = 1.0 / p.rho;
   double k2 = 0.0;
 #pragma unroll
   for (int j = 0; j < DIM; ++j) {
-    p.u[j] = q[2 + j] / p.rho;
+    p.u[j] = q[2 + j] * ri;
     k2 = fma(p.u[j], p.u[j], k2);
   }
   p.kin = 0.5 * k2;
@@ -81,8 +242,7 @@ __device__ __forceinline__ void closure(const KArgs& A, const double* q, Prim& p
   const double pi = al * A.pi1 + (1.0 - al) * A.pi2;
   p.P = (rhoe - pi) / xi;
   p.c = sqrt(((1.0 + xi) * p.P + pi) / (xi * p.rho));
-  p.rH1 = A.gh1 * (p.P + A.pinf1);
-  p.rH2 = A.gh2 * (p.P + A.pinf2);
+  p.sE = A.gh1 * (p.P + A.pinf1) - A.gh2 * (p.P + A.pinf2);
 }
 
 // Scalar s_q of the interface-capturing flux s_q a_1 for the conservative
@@ -94,7 +254,7 @@ __device__ __forceinline__ double s_coef(const KArgs& A, const Prim& p, int q) {
   if (q == 0) return A.rho01;
   if (q == 1) return -A.rho02;
   if (q < 2 + DIM) return dr * p.u[q - 2];
-  return dr * p.kin + p.rH1 - p.rH2;
+  return dr * p.kin + p.sE;
 }
 
 // Convective flux of conservative equation q along axis k.
@@ -105,63 +265,49 @@ __device__ __forceinline__ double conv_flux(const double* q, const Prim& p, int 
   return (q[2 + DIM] + p.P) * p.u[k];
 }
 
-// 4-point derivative contraction along the lane stride S = 4^k:
-// sum_b D[a_k][b] f(.., b, ..); Dr = row a_k of D.
-__device__ __forceinline__ double contract(double f, int lane, int ak, int S, const double* Dr) {
-  const int base = lane - ak * S;
-  double r = Dr[0] * __shfl(f, base);
-  r = fma(Dr[1], __shfl(f, base + S), r);
-  r = fma(Dr[2], __shfl(f, base + 2 * S), r);
-  r = fma(Dr[3], __shfl(f, base + 3 * S), r);
-  return r;
-}
-
 // Index of a node inside the face layer normal to axis k (axis k removed).
 __device__ __forceinline__ int face_index(int node, int k) {
   const int lowmask = (1 << (2 * k)) - 1;
   return (node & lowmask) | ((node >> (2 * k + 2)) << (2 * k));
 }
 
-// Per-lane element-local quantities shared by the ingredient and stage passes.
+// Element-local gradient quantities of a node.
 template <int DIM, bool VISC>
-struct NodeState {
-  static constexpr int NF = DIM + 5;
-  double q[NF];
-  Prim pr;
-  double gA[DIM], gP[DIM], nh[DIM], a[DIM];
+struct Grad {
+  double gA[DIM], nh[DIM], a[DIM];
+  double upsi;  // u . grad psi
   double S[VISC ? DIM : 1][VISC ? DIM : 1];  // grad u + grad u^T - 2/3 div u I
   double mu;
 };
 
 template <int DIM, bool VISC>
-__device__ __forceinline__ void element_quantities(const KArgs& A, NodeState<DIM, VISC>& s,
-                                                   int lane, const int* ak,
-                                                   const double (*Dr)[4]) {
-  closure<DIM>(A, s.q, s.pr);
-  const double al = s.q[3 + DIM];
-  const double ps = s.q[4 + DIM];
+__device__ __forceinline__ void gradients(const KArgs& A, const double* q, const Prim& p,
+                                          const LaneD<DIM>& L, Grad<DIM, VISC>& g) {
+  const double al = q[3 + DIM];
+  const double ps = q[4 + DIM];
+  double gP[DIM];
   double g2 = 0.0;
+  g.upsi = 0.0;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
-    const int S = 1 << (2 * k);
-    s.gA[k] = contract(al, lane, ak[k], S, Dr[k]) * A.Jinv[k];
-    s.gP[k] = contract(ps, lane, ak[k], S, Dr[k]) * A.Jinv[k];
-    g2 = fma(s.gP[k], s.gP[k], g2);
+    g.gA[k] = dk<DIM>(al, k, L, A);
+    gP[k] = dk<DIM>(ps, k, L, A);
+    g2 = fma(gP[k], gP[k], g2);
+    g.upsi = fma(p.u[k], gP[k], g.upsi);
   }
-  const double nrm = sqrt(g2 + A.delta * A.delta);
+  const double inv = 1.0 / sqrt(g2 + A.delta * A.delta);
   const double aa = al * (1.0 - al);
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
-    s.nh[k] = s.gP[k] / nrm;
-    s.a[k] = A.Gamma * (A.eps * s.gA[k] - aa * s.nh[k]);
+    g.nh[k] = gP[k] * inv;
+    g.a[k] = A.Gamma * (A.eps * g.gA[k] - aa * g.nh[k]);
   }
   if constexpr (VISC) {
     double gU[DIM][DIM];
 #pragma unroll
     for (int j = 0; j < DIM; ++j)
 #pragma unroll
-      for (int k = 0; k < DIM; ++k)
-        gU[j][k] = contract(s.pr.u[j], lane, ak[k], 1 << (2 * k), Dr[k]) * A.Jinv[k];
+      for (int k = 0; k < DIM; ++k) gU[j][k] = dk<DIM>(p.u[j], k, L, A);
     double div = 0.0;
 #pragma unroll
     for (int j = 0; j < DIM; ++j) div += gU[j][j];
@@ -169,93 +315,254 @@ __device__ __forceinline__ void element_quantities(const KArgs& A, NodeState<DIM
     for (int j = 0; j < DIM; ++j)
 #pragma unroll
       for (int k = 0; k < DIM; ++k)
-        s.S[j][k] = gU[j][k] + gU[k][j] - (j == k ? (2.0 / 3.0) * div : 0.0);
-    s.mu = A.mu1 * al + A.mu2 * (1.0 - al);
+        g.S[j][k] = gU[j][k] + gU[k][j] - (j == k ? (2.0 / 3.0) * div : 0.0);
+    g.mu = A.mu1 * al + A.mu2 * (1.0 - al);
   } else {
-    s.mu = 0.0;
+    g.mu = 0.0;
   }
 }
 
-template <int DIM>
-__device__ __forceinline__ void lane_setup(const KArgs& A, int node, int* ak, double (*Dr)[4]) {
+// ---- reduction helpers -----------------------------------------------------------
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Per-node record contributions of a state (time-step rate and monitors).
+template <int DIM, bool VISC>
+__device__ __forceinline__ void node_record(const KArgs& A, const double* q, const Prim& p, int node,
+                                            bool valid, double* v) {
+  constexpr int NF = DIM + 5;
+  double w = DIM * p.c;
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) w += fabs(p.u[j]);
+  const double al = q[3 + DIM];
+  double nu = 0.0;
+  if constexpr (VISC) nu = (A.mu1 * al + A.mu2 * (1.0 - al)) / p.rho;
+  const double xi = al * A.xi1 + (1.0 - al) * A.xi2;
+  const double pi = al * A.pi1 + (1.0 - al) * A.pi2;
+  const bool bad = !(p.rho > 0.0) || !(xi * p.rho > 0.0) || !((1.0 + xi) * p.P + pi > 0.0) ||
+                   !isfinite(p.P) || !isfinite(p.c);
+  double du = 0.0;
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) du = fmax(du, fabs(p.u[j] - A.u_ref[j]));
+  double W = 1.0;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
-    ak[k] = (node >> (2 * k)) & 3;
+    const int a = (node >> (2 * k)) & 3;
+    W *= sel4(a, GLL.w[0], GLL.w[1], GLL.w[2], GLL.w[3]) * A.J[k];
+  }
+  v[R_WAVE] = valid ? w : 0.0;
+  v[R_NU] = valid ? nu : 0.0;
+  v[R_AMIN] = valid ? al : INFINITY;
+  v[R_AMAX] = valid ? al : -INFINITY;
+  v[R_BAD] = (valid && bad) ? 1.0 : 0.0;
+  v[R_DEVP] = valid ? fabs(p.P - A.p_ref) : 0.0;
+  v[R_DEVU] = valid ? du : 0.0;
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
-      Dr[k][b] = sel4(ak[k], A.D[0][b], A.D[1][b], A.D[2][b], A.D[3][b]);
+  for (int f = 0; f < 8; ++f) v[R_INT + f] = (valid && f < NF) ? W * q[f] : 0.0;
+}
+
+__device__ __forceinline__ double rec_combine(int slot, double a, double b) {
+  if (slot == R_AMIN) return fmin(a, b);
+  if (slot == R_WAVE || slot == R_NU || slot == R_AMAX || slot == R_DEVP || slot == R_DEVU) return fmax(a, b);
+  return a + b;
+}
+__device__ __forceinline__ double rec_wave(int slot, double v) {
+  if (slot == R_AMIN) return wave_min(v);
+  if (slot == R_WAVE || slot == R_NU || slot == R_AMAX || slot == R_DEVP || slot == R_DEVU) return wave_max(v);
+  return wave_sum(v);
+}
+
+// Reduce-scatter of NS per-lane values over the wave (NS a power of two,
+// 8 or 16): butterfly over lane masks 32, 16, ... that halves the number of
+// slots a lane carries at every step, then a plain butterfly over the
+// remaining mask bits.  Afterwards every lane l holds the wave-wide result of
+// slot l >> (6 - log2 NS).  OP: 0 = sum, 1 = max.
+template <int HALF, int OP>
+__device__ __forceinline__ void rs_step(double* v, int m, bool upper) {
+#pragma unroll
+  for (int i = 0; i < HALF; ++i) {
+    const double lo = v[i], hi = v[HALF + i];
+    const double send = upper ? lo : hi;
+    const double keep = upper ? hi : lo;
+    const double got = __shfl_xor(send, m);
+    v[i] = OP == 0 ? keep + got : fmax(keep, got);
+  }
+}
+template <int OP>
+__device__ __forceinline__ double bfly(double x, int m) {
+  const double got = __shfl_xor(x, m);
+  return OP == 0 ? x + got : fmax(x, got);
+}
+template <int NS, int OP>
+__device__ __forceinline__ double wave_reduce_scatter(double* v) {
+  const int lane = __lane_id();
+  if constexpr (NS == 16) {
+    rs_step<8, OP>(v, 32, (lane & 32) != 0);
+    rs_step<4, OP>(v, 16, (lane & 16) != 0);
+    rs_step<2, OP>(v, 8, (lane & 8) != 0);
+    rs_step<1, OP>(v, 4, (lane & 4) != 0);
+    return bfly<OP>(bfly<OP>(v[0], 2), 1);
+  } else {
+    static_assert(NS == 8, "reduce-scatter of 8 or 16 slots");
+    rs_step<4, OP>(v, 32, (lane & 32) != 0);
+    rs_step<2, OP>(v, 16, (lane & 16) != 0);
+    rs_step<1, OP>(v, 8, (lane & 8) != 0);
+    return bfly<OP>(bfly<OP>(bfly<OP>(v[0], 4), 2), 1);
+  }
+}
+
+// Workgroup reduction of per-lane records into rec[blk * REC + slot] (fixed order).
+__device__ __forceinline__ void block_record(double* v, double* rec, long long blk) {
+  __shared__ double sh[REC][BLOCK / 64];
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  // max group: wave, nu, -min alpha, max alpha, dev p, dev u (padded to 8)
+  double mx[8] = {v[R_WAVE], v[R_NU], -v[R_AMIN], v[R_AMAX], v[R_DEVP], v[R_DEVU], -INFINITY, -INFINITY};
+  // sum group: non-physical count and the 8 integral slots (padded to 16)
+  double sm[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) sm[i] = 0.0;
+  sm[0] = v[R_BAD];
+#pragma unroll
+  for (int f = 0; f < 8; ++f) sm[1 + f] = v[R_INT + f];
+  const double xm = wave_reduce_scatter<8, 1>(mx);
+  const double xs = wave_reduce_scatter<16, 0>(sm);
+  if ((lane & 7) == 0) {
+    // slots 0..5 of the max group: R_WAVE, R_NU, R_AMIN, R_AMAX, R_DEVP, R_DEVU
+    const int slot = lane >> 3;
+    const int dst = slot < 4 ? slot : slot + (R_DEVP - 4);
+    if (slot < 6) sh[dst][w] = slot == 2 ? -xm : xm;
+  }
+  if ((lane & 3) == 0) {
+    const int slot = lane >> 2;
+    if (slot == 0) sh[R_BAD][w] = xs;
+    else if (slot <= 8) sh[R_INT + slot - 1][w] = xs;
+  }
+  __syncthreads();
+  if (threadIdx.x < REC) {
+    const int s = threadIdx.x;
+    double x = sh[s][0];
+#pragma unroll
+    for (int i = 1; i < BLOCK / 64; ++i) x = rec_combine(s, x, sh[s][i]);
+    rec[blk * REC + s] = x;
+  }
+}
+
+// Logical workgroup of this physical workgroup (XCD-aware order); -1 if padding.
+__device__ __forceinline__ long long logical_block(const KArgs& A) {
+  const long long i = blockIdx.x;
+  const long long lb = (i & 7) * A.xcd_chunk + (i >> 3);
+  return lb < A.nblocks ? lb : -1;
+}
+
+// ---- epilogue: face ingredients and records of a state held per lane ----------------
+template <int DIM, bool VISC, bool WRITE_G, bool WRITE_REC>
+__device__ __forceinline__ void emit(const KArgs& A, const double* q, long long e, bool valid, int node,
+                                     const int* ak, const LaneD<DIM>& L, double* G, double* rec,
+                                     long long blk) {
+  constexpr int NN = 1 << (2 * DIM);
+  constexpr int NFN = NN / 4;
+  constexpr int C = VISC ? 1 + DIM : 1;
+  Prim p;
+  closure<DIM>(A, q, p);
+  if constexpr (WRITE_G) {
+    Grad<DIM, VISC> g;
+    gradients<DIM, VISC>(A, q, p, L, g);
+    if (valid) {
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        if (ak[k] != 0 && ak[k] != 3) continue;
+        const int side = ak[k] == 3;
+        const int fn = face_index(node, k);
+        const long long base = (long long)((2 * k + side) * C) * A.E;
+        G[(base + e) * NFN + fn] = g.a[k];
+        if constexpr (VISC) {
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) G[(base + (long long)(1 + j) * A.E + e) * NFN + fn] = g.mu * g.S[j][k];
+        }
+      }
+    }
+  }
+  if constexpr (WRITE_REC) {
+    double v[REC];
+    node_record<DIM, VISC>(A, q, p, node, valid, v);
+    block_record(v, rec, blk);
   }
 }
 
 // ---------------------------------------------------------------------------
-// Face-ingredient pass: for every element and each of its 2d faces, the
-// normal component along +e_k of the interface flux a (and of the viscous
-// stress tau[j][k]) at the face nodes.  G[((2k+side)*C + comp)*E + e][fn].
+// Ingredient pass: G and records of a state (first stage of a step, residual).
 template <int DIM, bool VISC>
-__global__ __launch_bounds__(64) void k_face_ingredients(KArgs A, const double* __restrict__ U,
-                                                         double* __restrict__ G) {
+__global__ __launch_bounds__(BLOCK) void k_ingredients(KArgs A, const double* __restrict__ U,
+                                                       double* __restrict__ G, double* __restrict__ rec) {
   constexpr int NN = 1 << (2 * DIM);
   constexpr int EPW = 64 / NN;
   constexpr int NF = DIM + 5;
-  constexpr int C = VISC ? 1 + DIM : 1;
-  constexpr int NFN = NN / 4;
-  const int lane = threadIdx.x;
-  const long long e0 = (long long)blockIdx.x * EPW + lane / NN;
+  const long long blk = logical_block(A);
+  if (blk < 0) return;
+  const int lane = threadIdx.x & 63;
+  const long long e0 = (blk * (BLOCK / 64) + (threadIdx.x >> 6)) * EPW + lane / NN;
   const bool valid = e0 < A.E;
   const long long e = valid ? e0 : A.E - 1;
   const int node = lane % NN;
-  int ak[3];
-  double Dr[3][4];
-  lane_setup<DIM>(A, node, ak, Dr);
-  NodeState<DIM, VISC> s;
+  int ak[3] = {0, 0, 0};
 #pragma unroll
-  for (int f = 0; f < NF; ++f) s.q[f] = U[(f * A.E + e) * NN + node];
-  element_quantities<DIM, VISC>(A, s, lane, ak, Dr);
-  if (!valid) return;
+  for (int k = 0; k < DIM; ++k) ak[k] = (node >> (2 * k)) & 3;
+  LaneD<DIM> L;
+  lane_coeffs<DIM>(A, ak, L);
+  double q[NF];
 #pragma unroll
-  for (int k = 0; k < DIM; ++k) {
-    if (ak[k] != 0 && ak[k] != 3) continue;
-    const int side = ak[k] == 3;
-    const int fn = face_index(node, k);
-    const long long base = (long long)((2 * k + side) * C) * A.E;
-    G[(base + e) * NFN + fn] = s.a[k];
-    if constexpr (VISC) {
-#pragma unroll
-      for (int j = 0; j < DIM; ++j) G[(base + (long long)(1 + j) * A.E + e) * NFN + fn] = s.mu * s.S[j][k];
-    }
-  }
+  for (int f = 0; f < NF; ++f) q[f] = U[(f * A.E + e) * NN + node];
+  emit<DIM, VISC, true, true>(A, q, e, valid, node, ak, L, G, rec, blk);
 }
 
 // ---------------------------------------------------------------------------
-// Stage pass: residual of one element (volume terms, sources, all faces,
-// SIPG symmetric term), then either R is stored (MODE 0), or the RK stage
-// U_out = U_s + dt R (MODE 1), or U_out = rk_a U_n + rk_b (U_s + dt R) (MODE 2).
-template <int DIM, bool VISC, bool CSF, int MODE>
-__global__ __launch_bounds__(64) void k_stage(KArgs A, const double* __restrict__ Us,
-                                              const double* __restrict__ G,
-                                              const double* Un, double* Out,
-                                              const double* __restrict__ dtp) {
+// Stage pass: residual of each element (volume terms, sources, all faces, SIPG
+// symmetric term), then MODE 0: store R; MODE 1: U_out = U_s + dt R;
+// MODE 2: U_out = rk_a U_n + rk_b (U_s + dt R).  Epilogue on U_out: EPI = 1
+// face ingredients into Gout, EPI = 2 also the reduction records.
+template <int DIM, bool VISC, bool CSF, bool DIRI, int MODE, int EPI>
+__global__ __launch_bounds__(BLOCK) void k_stage(KArgs A, StageIO io) {
   constexpr int NN = 1 << (2 * DIM);
   constexpr int EPW = 64 / NN;
   constexpr int NF = DIM + 5;
   constexpr int NC = DIM + 3;  // conservative equations
   constexpr int C = VISC ? 1 + DIM : 1;
   constexpr int NFN = NN / 4;
-  const int lane = threadIdx.x;
-  const long long e0 = (long long)blockIdx.x * EPW + lane / NN;
+  const long long blk = logical_block(A);
+  if (blk < 0) return;
+  const int lane = threadIdx.x & 63;
+  const long long e0 = (blk * (BLOCK / 64) + (threadIdx.x >> 6)) * EPW + lane / NN;
   const bool valid = e0 < A.E;
   const long long e = valid ? e0 : A.E - 1;
   const int node = lane % NN;
-  int ak[3];
-  double Dr[3][4];
-  lane_setup<DIM>(A, node, ak, Dr);
-
-  NodeState<DIM, VISC> s;
+  int ak[3] = {0, 0, 0};
 #pragma unroll
-  for (int f = 0; f < NF; ++f) s.q[f] = Us[(f * A.E + e) * NN + node];
-  element_quantities<DIM, VISC>(A, s, lane, ak, Dr);
-  const double* q = s.q;
-  const Prim& pr = s.pr;
+  for (int k = 0; k < DIM; ++k) ak[k] = (node >> (2 * k)) & 3;
+  LaneD<DIM> L;
+  lane_coeffs<DIM>(A, ak, L);
+
+  const double* __restrict__ Us = io.Us;
+  double q[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) q[f] = Us[(f * A.E + e) * NN + node];
+  Prim pr;
+  closure<DIM>(A, q, pr);
+  Grad<DIM, VISC> g;
+  gradients<DIM, VISC>(A, q, pr, L, g);
 
   double R[NF];
   // volume terms, strong form: R_q = sum_k (1/J_k) D_k (-F_q + s_q a + V_q)_k
@@ -265,31 +572,30 @@ __global__ __launch_bounds__(64) void k_stage(KArgs A, const double* __restrict_
     double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-      double fl = -conv_flux<DIM>(q, pr, qi, k) + sq * s.a[k];
+      double fl = fma(sq, g.a[k], -conv_flux<DIM>(q, pr, qi, k));
       if constexpr (VISC) {
         if (qi >= 2 && qi < 2 + DIM) {
-          fl += s.mu * s.S[qi - 2][k];
+          fl = fma(g.mu, g.S[qi - 2][k], fl);
         } else if (qi == 2 + DIM) {
           double tu = 0.0;
 #pragma unroll
-          for (int j = 0; j < DIM; ++j) tu = fma(s.S[j][k], pr.u[j], tu);
-          fl += s.mu * tu;
+          for (int j = 0; j < DIM; ++j) tu = fma(g.S[j][k], pr.u[j], tu);
+          fl = fma(g.mu, tu, fl);
         }
       }
-      acc += contract(fl, lane, ak[k], 1 << (2 * k), Dr[k]) * A.Jinv[k];
+      acc += dk<DIM>(fl, k, L, A);
     }
     R[qi] = acc;
   }
   {
-    double acc = 0.0, ua = 0.0, up = 0.0;
+    double acc = 0.0, ua = 0.0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-      acc += contract(s.a[k], lane, ak[k], 1 << (2 * k), Dr[k]) * A.Jinv[k];
-      ua = fma(pr.u[k], s.gA[k], ua);
-      up = fma(pr.u[k], s.gP[k], up);
+      acc += dk<DIM>(g.a[k], k, L, A);
+      ua = fma(pr.u[k], g.gA[k], ua);
     }
-    R[3 + DIM] = -ua + acc;  // transport as a volume source + div a
-    R[4 + DIM] = -up;
+    R[3 + DIM] = acc - ua;  // div a, and transport as a volume source
+    R[4 + DIM] = -g.upsi;
   }
   // sources: gravity and CSF surface tension
   {
@@ -298,8 +604,8 @@ __global__ __launch_bounds__(64) void k_stage(KArgs A, const double* __restrict_
       double div = 0.0, ga2 = 0.0;
 #pragma unroll
       for (int k = 0; k < DIM; ++k) {
-        div += contract(s.nh[k], lane, ak[k], 1 << (2 * k), Dr[k]) * A.Jinv[k];
-        ga2 = fma(s.gA[k], s.gA[k], ga2);
+        div += dk<DIM>(g.nh[k], k, L, A);
+        ga2 = fma(g.gA[k], g.gA[k], ga2);
       }
       const double kappa = -div;
       const double dG = sqrt(ga2 + A.delta * A.delta) - A.delta;
@@ -312,8 +618,8 @@ __global__ __launch_bounds__(64) void k_stage(KArgs A, const double* __restrict_
         double sj = pr.rho * A.grav[j];
         double ej = pr.rho * A.grav[j] * pr.u[j];
         if constexpr (CSF) {
-          sj += csf * s.nh[j];
-          ej += csf * pr.u[j] * s.nh[j];
+          sj += csf * g.nh[j];
+          ej += csf * pr.u[j] * g.nh[j];
         }
         R[2 + j] += sj;
         ew += ej;
@@ -323,7 +629,7 @@ __global__ __launch_bounds__(64) void k_stage(KArgs A, const double* __restrict_
   }
 
   // faces
-  long long ec[3];
+  long long ec[3] = {0, 0, 0};
   {
     long long r = e;
 #pragma unroll
@@ -332,6 +638,7 @@ __global__ __launch_bounds__(64) void k_stage(KArgs A, const double* __restrict_
       r /= A.N[k];
     }
   }
+  const double* __restrict__ Gin = io.Gin;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
     const int S = 1 << (2 * k);
@@ -364,37 +671,40 @@ __global__ __launch_bounds__(64) void k_stage(KArgs A, const double* __restrict_
         for (int f = 0; f < NF; ++f) qe[f] = Us[(f * A.E + en) * NN + nodee];
         const int fn = face_index(node, k);
         const long long gb = (long long)((2 * k + 1 - side) * C) * A.E;
-        aek = G[(gb + en) * NFN + fn];
+        aek = Gin[(gb + en) * NFN + fn];
         if constexpr (VISC) {
 #pragma unroll
-          for (int j = 0; j < DIM; ++j) tek[j] = G[(gb + (long long)(1 + j) * A.E + en) * NFN + fn];
+          for (int j = 0; j < DIM; ++j) tek[j] = Gin[(gb + (long long)(1 + j) * A.E + en) * NFN + fn];
         }
       } else {
         const int kind = A.bc[k][side];
 #pragma unroll
         for (int f = 0; f < NF; ++f) qe[f] = q[f];
+        aek = g.a[k];
+        if constexpr (VISC) {
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) tek[j] = g.mu * g.S[j][k];
+        }
         if (kind == DG2P_BC_SLIP_WALL) {
           qe[2 + k] = -q[2 + k];
-          aek = -s.a[k];
+          aek = -g.a[k];
           if constexpr (VISC) {
 #pragma unroll
-            for (int j = 0; j < DIM; ++j) tek[j] = (j == k ? 1.0 : -1.0) * (s.mu * s.S[j][k]);
+            for (int j = 0; j < DIM; ++j)
+              if (j != k) tek[j] = -tek[j];
           }
-        } else if (kind == DG2P_BC_DIRICHLET) {
+        }
+        if constexpr (DIRI) {
+          if (kind == DG2P_BC_DIRICHLET) {
 #pragma unroll
-          for (int f = 0; f < 4 + DIM; ++f) qe[f] = A.bcs[k][side][f];
-          const double ag = qe[3 + DIM];
-          aek = A.Gamma * (A.eps * s.gA[k] - (ag * (1.0 - ag)) * s.nh[k]);
-          if constexpr (VISC) {
-            const double mug = A.mu1 * ag + A.mu2 * (1.0 - ag);
+            for (int f = 0; f < 4 + DIM; ++f) qe[f] = A.bcs[k][side][f];
+            const double ag = qe[3 + DIM];
+            aek = A.Gamma * (A.eps * g.gA[k] - (ag * (1.0 - ag)) * g.nh[k]);
+            if constexpr (VISC) {
+              const double mug = A.mu1 * ag + A.mu2 * (1.0 - ag);
 #pragma unroll
-            for (int j = 0; j < DIM; ++j) tek[j] = mug * s.S[j][k];
-          }
-        } else {  // extrapolate
-          aek = s.a[k];
-          if constexpr (VISC) {
-#pragma unroll
-            for (int j = 0; j < DIM; ++j) tek[j] = s.mu * s.S[j][k];
+              for (int j = 0; j < DIM; ++j) tek[j] = mug * g.S[j][k];
+            }
           }
         }
       }
@@ -402,15 +712,15 @@ __global__ __launch_bounds__(64) void k_stage(KArgs A, const double* __restrict_
       closure<DIM>(A, qe, pe);
       const double umI = sm * pr.u[k], umE = sm * pe.u[k];
       const double lam = fmax(fabs(umI) + pr.c, fabs(umE) + pe.c);
-      const double amI = sm * s.a[k], amE = sm * aek;
+      const double amI = sm * g.a[k], amE = sm * aek;
       const double alI = q[3 + DIM], alE = qe[3 + DIM];
       const double jump = alI - alE;
       const double ahat = 0.5 * (amI + amE) - A.pen[k] * A.GammaEps * jump;
-      const double L = A.lift[k];
-      double mue = 0.0, etav = 0.0;
+      const double Lf = A.lift[k];
+      double etav = 0.0;
       if constexpr (VISC) {
-        mue = A.mu1 * alE + A.mu2 * (1.0 - alE);
-        etav = A.pen[k] * (0.5 * (s.mu + mue));
+        const double mue = A.mu1 * alE + A.mu2 * (1.0 - alE);
+        etav = A.pen[k] * (0.5 * (g.mu + mue));
       }
 #pragma unroll
       for (int qi = 0; qi < NC; ++qi) {
@@ -425,14 +735,14 @@ __global__ __launch_bounds__(64) void k_stage(KArgs A, const double* __restrict_
             double VmI, VmE, pen;
             if (qi < 2 + DIM) {
               const int j = qi - 2;
-              VmI = sm * (s.mu * s.S[j][k]);
+              VmI = sm * (g.mu * g.S[j][k]);
               VmE = sm * tek[j];
               pen = etav * (pr.u[j] - pe.u[j]);
             } else {
               double tuI = 0.0, tuE = 0.0, du = 0.0;
 #pragma unroll
               for (int j = 0; j < DIM; ++j) {
-                tuI += (s.mu * s.S[j][k]) * pr.u[j];
+                tuI += (g.mu * g.S[j][k]) * pr.u[j];
                 tuE += tek[j] * pe.u[j];
                 du += (pr.u[j] - pe.u[j]) * (0.5 * (pr.u[j] + pe.u[j]));
               }
@@ -444,44 +754,60 @@ __global__ __launch_bounds__(64) void k_stage(KArgs A, const double* __restrict_
             t += Vhat - VmI;
           }
         }
-        R[qi] += L * t;
+        R[qi] += Lf * t;
         symv[qi] = sm * sbar * A.GammaEps * jump;
       }
       const double KA = 0.5 * (lam - umI) * (alE - alI);
-      R[3 + DIM] += L * (KA + (ahat - amI));
+      R[3 + DIM] += Lf * (KA + (ahat - amI));
       symv[NC] = sm * A.GammaEps * jump;
-      R[4 + DIM] += L * (0.5 * (lam - umI) * (qe[4 + DIM] - q[4 + DIM]));
+      R[4 + DIM] += Lf * (0.5 * (lam - umI) * (qe[4 + DIM] - q[4 + DIM]));
     }
     // SIPG symmetric term, spread along the normal line through each face node
-    const int base = lane - akk * S;
-    const double wlo = sel4(akk, A.symw[k][0][0], A.symw[k][0][1], A.symw[k][0][2], A.symw[k][0][3]);
-    const double whi = sel4(akk, A.symw[k][1][0], A.symw[k][1][1], A.symw[k][1][2], A.symw[k][1][3]);
+    // D[end][a] / (2 w_a J_k^2), end = 0 (low face) or 3 (high face)
+    const double wlo = sel4(akk, GLL.D[0][0] / GLL.w[0], GLL.D[0][1] / GLL.w[1], GLL.D[0][2] / GLL.w[2],
+                            GLL.D[0][3] / GLL.w[3]) * A.hJ2inv[k];
+    const double whi = sel4(akk, GLL.D[3][0] / GLL.w[0], GLL.D[3][1] / GLL.w[1], GLL.D[3][2] / GLL.w[2],
+                            GLL.D[3][3] / GLL.w[3]) * A.hJ2inv[k];
 #pragma unroll
     for (int i = 0; i <= NC; ++i) {
-      const double lo = __shfl(symv[i], base);
-      const double hi = __shfl(symv[i], base + 3 * S);
+      double lo, hi;
+      if (k == 0) {
+        lo = line_end<0>(symv[i], akk, false);
+        hi = line_end<0>(symv[i], akk, true);
+      } else if (k == 1) {
+        lo = line_end<1>(symv[i], akk, false);
+        hi = line_end<1>(symv[i], akk, true);
+      } else {
+        lo = line_end<2>(symv[i], akk, false);
+        hi = line_end<2>(symv[i], akk, true);
+      }
       const int f = (i < NC) ? i : 3 + DIM;
-      R[f] += lo * wlo + hi * whi;
+      R[f] = fma(lo, wlo, fma(hi, whi, R[f]));
     }
   }
 
-  if (!valid) return;
   const long long o = e * NN + node;
+  const long long fs = A.E * NN;
   if constexpr (MODE == 0) {
+    if (valid) {
 #pragma unroll
-    for (int f = 0; f < NF; ++f) Out[f * A.E * NN + o] = R[f];
+      for (int f = 0; f < NF; ++f) io.Out[f * fs + o] = R[f];
+    }
   } else {
-    const double dt = *dtp;
+    const double dt = *io.dt;
+    double uo[NF];
     if constexpr (MODE == 1) {
 #pragma unroll
-      for (int f = 0; f < NF; ++f) Out[f * A.E * NN + o] = q[f] + dt * R[f];
+      for (int f = 0; f < NF; ++f) uo[f] = q[f] + dt * R[f];
     } else {
 #pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        const double un = Un[f * A.E * NN + o];
-        Out[f * A.E * NN + o] = A.rk_a * un + A.rk_b * (q[f] + dt * R[f]);
-      }
+      for (int f = 0; f < NF; ++f) uo[f] = A.rk_a * io.Un[f * fs + o] + A.rk_b * (q[f] + dt * R[f]);
     }
+    if (valid) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) io.Out[f * fs + o] = uo[f];
+    }
+    if constexpr (EPI > 0) emit<DIM, VISC, true, (EPI > 1)>(A, uo, e, valid, node, ak, L, io.Gout, io.rec, blk);
   }
 }
 
@@ -513,219 +839,97 @@ __global__ void k_prim_to_cons(KArgs A, const double* __restrict__ P, double* __
 }
 
 // ---------------------------------------------------------------------------
-// Reductions.  Block size 256, fixed grid (RED_BLOCKS), fixed order: the
-// results are bitwise reproducible.
-constexpr int RED_THREADS = 256;
-constexpr int RED_BLOCKS = 1024;
-constexpr int MON_SLOTS = 16;  // per-block partial record of the monitor pass
-
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
-}
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-  return v;
-}
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-
+// Records of a state without face ingredients (dt / monitor requests):
+// grid-stride over nodes, fixed grid.
 template <int DIM, bool VISC>
-__global__ __launch_bounds__(RED_THREADS) void k_rate_partial(KArgs A, const double* __restrict__ U,
-                                                              double* __restrict__ part) {
+__global__ __launch_bounds__(BLOCK) void k_records(KArgs A, const double* __restrict__ U,
+                                                   double* __restrict__ rec) {
   constexpr int NN = 1 << (2 * DIM);
+  constexpr int NF = DIM + 5;
   const long long n = A.E * NN;
-  double mw = 0.0, mn = 0.0;
-  for (long long i = (long long)blockIdx.x * RED_THREADS + threadIdx.x; i < n;
-       i += (long long)gridDim.x * RED_THREADS) {
-    double q[DIM + 5];
+  double acc[REC];
 #pragma unroll
-    for (int f = 0; f < DIM + 4; ++f) q[f] = U[f * n + i];
-    q[DIM + 4] = 0.0;
+  for (int s = 0; s < REC; ++s) acc[s] = (s == R_AMIN) ? INFINITY : (s == R_AMAX ? -INFINITY : 0.0);
+  // the loop bound depends on the workgroup only, so every thread reaches the reduction
+  for (long long base = (long long)blockIdx.x * BLOCK; base < n; base += (long long)gridDim.x * BLOCK) {
+    const long long i = base + threadIdx.x;
+    const bool valid = i < n;
+    const long long ii = valid ? i : 0;
+    double q[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) q[f] = U[f * n + ii];
     Prim p;
     closure<DIM>(A, q, p);
-    double w = DIM * p.c;
+    double v[REC];
+    node_record<DIM, VISC>(A, q, p, (int)(ii % NN), valid, v);
 #pragma unroll
-    for (int j = 0; j < DIM; ++j) w += fabs(p.u[j]);
-    mw = fmax(mw, w);
-    if constexpr (VISC) {
-      const double al = q[3 + DIM];
-      mn = fmax(mn, (A.mu1 * al + A.mu2 * (1.0 - al)) / p.rho);
-    }
+    for (int s = 0; s < REC; ++s) acc[s] = rec_combine(s, acc[s], v[s]);
   }
-  __shared__ double sh[2][RED_THREADS / 64];
-  mw = wave_max(mw);
-  mn = wave_max(mn);
-  if ((threadIdx.x & 63) == 0) {
-    sh[0][threadIdx.x >> 6] = mw;
-    sh[1][threadIdx.x >> 6] = mn;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double a = sh[0][0], b = sh[1][0];
-    for (int i = 1; i < RED_THREADS / 64; ++i) {
-      a = fmax(a, sh[0][i]);
-      b = fmax(b, sh[1][i]);
-    }
-    part[2 * blockIdx.x] = a;
-    part[2 * blockIdx.x + 1] = b;
-  }
+  block_record(acc, rec, blockIdx.x);
 }
 
-// nu_max = max(Gamma eps, max mu/rho); rate = (max wave + (p+1)^2 d nu_max / h_min) / h_min.
-__global__ __launch_bounds__(RED_THREADS) void k_rate_final(const double* __restrict__ part, int nblk,
-                                                            double GammaEps, int dim, double hmin,
-                                                            double cfl, double* dt,
-                                                            dg2p_monitors* mon) {
-  double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += RED_THREADS) {
-    a = fmax(a, part[2 * i]);
-    b = fmax(b, part[2 * i + 1]);
+// First-level reduction of records: workgroup j combines records
+// [j*chunk, min((j+1)*chunk, n)) in index order.
+__global__ __launch_bounds__(BLOCK) void k_reduce_records(const double* __restrict__ rec, long long n,
+                                                          long long chunk, double* __restrict__ out) {
+  const long long lo = (long long)blockIdx.x * chunk;
+  const long long hi = lo + chunk < n ? lo + chunk : n;
+  double acc[REC];
+#pragma unroll
+  for (int s = 0; s < REC; ++s) acc[s] = (s == R_AMIN) ? INFINITY : (s == R_AMAX ? -INFINITY : 0.0);
+  for (long long r = lo + threadIdx.x; r < hi; r += BLOCK) {
+#pragma unroll
+    for (int s = 0; s < REC; ++s) acc[s] = rec_combine(s, acc[s], rec[r * REC + s]);
   }
-  __shared__ double sh[2][RED_THREADS / 64];
-  a = wave_max(a);
-  b = wave_max(b);
-  if ((threadIdx.x & 63) == 0) {
-    sh[0][threadIdx.x >> 6] = a;
-    sh[1][threadIdx.x >> 6] = b;
+  block_record(acc, out, blockIdx.x);
+}
+
+// Final reduction: time-step rule and monitors.  rate = (max wave + (p+1)^2 d
+// nu_max / h_min) / h_min with nu_max = max(Gamma eps, max mu/rho); dt = cfl / rate.
+__global__ __launch_bounds__(BLOCK) void k_finalize(const double* __restrict__ rec, long long n,
+                                                    double GammaEps, int dim, int nf, double hmin,
+                                                    double cfl, const double* dt_fixed, double* dt,
+                                                    double* t, dg2p_monitors* mon) {
+  double acc[REC];
+#pragma unroll
+  for (int s = 0; s < REC; ++s) acc[s] = (s == R_AMIN) ? INFINITY : (s == R_AMAX ? -INFINITY : 0.0);
+  for (long long r = threadIdx.x; r < n; r += BLOCK) {
+#pragma unroll
+    for (int s = 0; s < REC; ++s) acc[s] = rec_combine(s, acc[s], rec[r * REC + s]);
+  }
+  __shared__ double red[REC];
+  __shared__ double sh[REC][BLOCK / 64];
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int s = 0; s < REC; ++s) {
+    const double x = rec_wave(s, acc[s]);
+    if ((threadIdx.x & 63) == 0) sh[s][w] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < REC) {
+    const int s = threadIdx.x;
+    double x = sh[s][0];
+    for (int i = 1; i < BLOCK / 64; ++i) x = rec_combine(s, x, sh[s][i]);
+    red[s] = x;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int i = 1; i < RED_THREADS / 64; ++i) {
-      sh[0][0] = fmax(sh[0][0], sh[0][i]);
-      sh[1][0] = fmax(sh[1][0], sh[1][i]);
-    }
-    const double nu = fmax(GammaEps, sh[1][0]);
-    const double rate = (sh[0][0] + 16.0 * dim * nu / hmin) / hmin;
-    const double d = cfl / rate;
+    const double nu = fmax(GammaEps, red[R_NU]);
+    const double rate = (red[R_WAVE] + 16.0 * dim * nu / hmin) / hmin;
+    const double d = dt_fixed ? *dt_fixed : cfl / rate;
     if (dt) *dt = d;
+    if (t) *t += d;
     if (mon) {
       mon->max_rate = rate;
       mon->dt = d;
+      mon->min_alpha = red[R_AMIN];
+      mon->max_alpha = red[R_AMAX];
+      for (int f = 0; f < 8; ++f) mon->integral[f] = f < nf ? red[R_INT + f] : 0.0;
+      mon->dev_p = red[R_DEVP];
+      mon->dev_u = red[R_DEVU];
+      mon->nonphys = (long long)red[R_BAD];
     }
   }
-}
-
-// Monitor partials per block: [0..NF) integrals, NF: min alpha, NF+1: max alpha,
-// NF+2: max |P - p_ref|, NF+3: max |u - u_ref|, NF+4: non-physical count.
-template <int DIM>
-__global__ __launch_bounds__(RED_THREADS) void k_monitor_partial(KArgs A, const double* __restrict__ U,
-                                                                 double p_ref, double ur0, double ur1,
-                                                                 double ur2, double* __restrict__ part) {
-  constexpr int NN = 1 << (2 * DIM);
-  constexpr int NF = DIM + 5;
-  const long long n = A.E * NN;
-  double acc[NF];
-#pragma unroll
-  for (int f = 0; f < NF; ++f) acc[f] = 0.0;
-  double amin = INFINITY, amax = -INFINITY, dp = 0.0, du = 0.0, bad = 0.0;
-  const double ur[3] = {ur0, ur1, ur2};
-  for (long long i = (long long)blockIdx.x * RED_THREADS + threadIdx.x; i < n;
-       i += (long long)gridDim.x * RED_THREADS) {
-    const int node = (int)(i % NN);
-    double W = 1.0;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      const int a = (node >> (2 * k)) & 3;
-      W *= sel4(a, A.wJ[k][0], A.wJ[k][1], A.wJ[k][2], A.wJ[k][3]);
-    }
-    double q[NF];
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      q[f] = U[f * n + i];
-      acc[f] = fma(W, q[f], acc[f]);
-    }
-    const double al = q[3 + DIM];
-    amin = fmin(amin, al);
-    amax = fmax(amax, al);
-    Prim p;
-    closure<DIM>(A, q, p);
-    const double xi = al * A.xi1 + (1.0 - al) * A.xi2;
-    const double pi = al * A.pi1 + (1.0 - al) * A.pi2;
-    const bool nonphys = !(p.rho > 0.0) || !(xi * p.rho > 0.0) || !((1.0 + xi) * p.P + pi > 0.0) ||
-                         !isfinite(p.P) || !isfinite(p.c);
-    bad += nonphys ? 1.0 : 0.0;
-    dp = fmax(dp, fabs(p.P - p_ref));
-#pragma unroll
-    for (int j = 0; j < DIM; ++j) du = fmax(du, fabs(p.u[j] - ur[j]));
-  }
-  __shared__ double sh[MON_SLOTS][RED_THREADS / 64];
-  const int w = threadIdx.x >> 6;
-#pragma unroll
-  for (int f = 0; f < NF; ++f) {
-    const double v = wave_sum(acc[f]);
-    if ((threadIdx.x & 63) == 0) sh[f][w] = v;
-  }
-  {
-    const double v0 = wave_min(amin), v1 = wave_max(amax), v2 = wave_max(dp), v3 = wave_max(du),
-                 v4 = wave_sum(bad);
-    if ((threadIdx.x & 63) == 0) {
-      sh[NF][w] = v0;
-      sh[NF + 1][w] = v1;
-      sh[NF + 2][w] = v2;
-      sh[NF + 3][w] = v3;
-      sh[NF + 4][w] = v4;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double* o = part + (long long)blockIdx.x * MON_SLOTS;
-    for (int f = 0; f < NF; ++f) {
-      double v = sh[f][0];
-      for (int i = 1; i < RED_THREADS / 64; ++i) v += sh[f][i];
-      o[f] = v;
-    }
-    double v0 = sh[NF][0], v1 = sh[NF + 1][0], v2 = sh[NF + 2][0], v3 = sh[NF + 3][0],
-           v4 = sh[NF + 4][0];
-    for (int i = 1; i < RED_THREADS / 64; ++i) {
-      v0 = fmin(v0, sh[NF][i]);
-      v1 = fmax(v1, sh[NF + 1][i]);
-      v2 = fmax(v2, sh[NF + 2][i]);
-      v3 = fmax(v3, sh[NF + 3][i]);
-      v4 += sh[NF + 4][i];
-    }
-    o[NF] = v0;
-    o[NF + 1] = v1;
-    o[NF + 2] = v2;
-    o[NF + 3] = v3;
-    o[NF + 4] = v4;
-  }
-}
-
-template <int DIM>
-__global__ __launch_bounds__(64) void k_monitor_final(const double* __restrict__ part, int nblk,
-                                                      dg2p_monitors* mon) {
-  constexpr int NF = DIM + 5;
-  // one lane per slot, blocks summed in index order (deterministic)
-  const int t = threadIdx.x;
-  if (t >= NF + 5) return;
-  double v = part[t];
-  for (int b = 1; b < nblk; ++b) {
-    const double x = part[(long long)b * MON_SLOTS + t];
-    if (t < NF || t == NF + 4)
-      v += x;
-    else if (t == NF)
-      v = fmin(v, x);
-    else
-      v = fmax(v, x);
-  }
-  if (t < NF)
-    mon->integral[t] = v;
-  else if (t == NF)
-    mon->min_alpha = v;
-  else if (t == NF + 1)
-    mon->max_alpha = v;
-  else if (t == NF + 2)
-    mon->dev_p = v;
-  else if (t == NF + 3)
-    mon->dev_u = v;
-  else
-    mon->nonphys = (long long)v;
 }
 
 }  // namespace dg2p

@@ -24,7 +24,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK, EINVAL, EHIP, ENONPHYS, EUNSUPPORTED, EWORKSPACE = 0, -1, -2, -3, -4, -5
 BC = {"periodic": 0, "slip_wall": 1, "dirichlet": 2, "extrapolate": 3}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
-OP_RHS, OP_RK_STEP, OP_MAX_DT, OP_MONITORS, OP_RHS_VJP, OP_RK_STEP_VJP = range(6)
+OP_RHS, OP_RK_STEP, OP_MAX_DT, OP_MONITORS, OP_RHS_VJP, OP_RK_STEP_VJP, OP_ADVANCE = range(7)
 
 
 class MeshDesc(ctypes.Structure):
@@ -68,6 +68,7 @@ _SIG = {
     "dg2p_max_dt": ([_vp, ctypes.POINTER(Params), _dp, _d, _dp, _vp, _vp, _vp], _i),
     "dg2p_rk_step": ([_vp, ctypes.POINTER(Params), _dp, _dp, _vp, _vp], _i),
     "dg2p_compute_monitors": ([_vp, ctypes.POINTER(Params), _dp, _d, _dp, _vp, _vp, _vp], _i),
+    "dg2p_advance": ([_vp, ctypes.POINTER(Params), _dp, _i, _d, _dp, _dp, _dp, _vp, _d, _vp, _vp, _vp], _i),
     "dg2p_timing_enable": ([_i], _i),
     "dg2p_timing_read": ([_i, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_longlong)], _i),
 }
@@ -234,6 +235,28 @@ def rk_step(mesh, params, U, dt, stream=None):
     return U
 
 
+def advance(mesh, params, U, n_steps, cfl=0.1, dt_fixed=None, t=None, dt_last=None, mon=None,
+            p_ref=0.0, u_ref=None, stream=None):
+    """n_steps SSP-RK3 steps in place with device-side dt (no host sync).
+    dt_fixed / t / dt_last: 1-element float64 device tensors (optional);
+    mon: float64 device tensor of MONITOR_DOUBLES (optional)."""
+    U = _as_state(mesh, U)
+    ws = mesh.workspace(params, OP_ADVANCE, U.device)
+    ur = (ctypes.c_double * 3)(*([0.0, 0.0, 0.0] if u_ref is None else (list(u_ref) + [0.0] * 3)[:3]))
+    _check(_lib.dg2p_advance(mesh.handle, ctypes.byref(params), _ptr(U), int(n_steps), float(cfl),
+                             _ptr(dt_fixed), _ptr(t), _ptr(dt_last), _ptr(mon), float(p_ref),
+                             ctypes.cast(ur, ctypes.c_void_p), ws, _stream(stream)), "dg2p_advance")
+    return U
+
+
+def decode_monitors(buf, nf):
+    raw = buf.detach().cpu().numpy()
+    m = Monitors.from_buffer_copy(raw.tobytes())
+    return dict(max_rate=m.max_rate, dt=m.dt, min_alpha=m.min_alpha, max_alpha=m.max_alpha,
+                integral=list(m.integral)[:nf], dev_p=m.dev_p, dev_u=m.dev_u,
+                nonphys=int(m.nonphys))
+
+
 def monitors(mesh, params, U, p_ref=0.0, u_ref=None, stream=None, sync=True):
     U = _as_state(mesh, U)
     buf = torch.zeros(MONITOR_DOUBLES, dtype=torch.float64, device=U.device)
@@ -244,11 +267,7 @@ def monitors(mesh, params, U, p_ref=0.0, u_ref=None, stream=None, sync=True):
            "dg2p_compute_monitors")
     if not sync:
         return buf
-    raw = buf.cpu().numpy()
-    m = Monitors.from_buffer_copy(raw.tobytes())
-    return dict(max_rate=m.max_rate, dt=m.dt, min_alpha=m.min_alpha, max_alpha=m.max_alpha,
-                integral=list(m.integral)[:mesh.nf], dev_p=m.dev_p, dev_u=m.dev_u,
-                nonphys=int(m.nonphys))
+    return decode_monitors(buf, mesh.nf)
 
 
 def timing_enable(on=True):
