@@ -134,6 +134,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the mixed-precision timings")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -195,6 +197,26 @@ def main():
     src = source_hash()
     traffic = recorded_traffic(args.workload, src)
 
+    # mixed-precision forms: same workload from the same initial state
+    variants = {}
+    if not args.no_variants:
+        for prec in ("fp32", "bf16"):
+            Pm = dg2p.make_params(cfg["params"], precision=prec)
+            Um = dg2p.prim_to_cons(mesh, P, dg2p.prim_tensor(
+                workloads.primitive_fields(cfg, mesh.node_coords()), cfg["dim"]))
+            dtm = torch.empty(1, dtype=torch.float64, device="cuda")
+            dg2p.advance(mesh, Pm, Um, args.warmup, cfl=args.cfl, dt_last=dtm)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            dg2p.advance(mesh, Pm, Um, args.steps, cfl=args.cfl, dt_last=dtm)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            msm = e0.elapsed_time(e1) / args.steps
+            variants[prec] = {"value": 3.0 * dof / (msm * 1e-3), "ms_per_step": msm,
+                              "speedup_vs_fp64": ms_step / msm,
+                              "contractions": prec, "closure_and_rk": "fp64"}
+            del Um
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg, args.cpu_seconds)
@@ -234,6 +256,7 @@ def main():
             "algorithmic_bytes_per_launch": alg_bytes,
         },
         "kernels_mean_ms": {k: v[0] for k, v in k_ms.items()},
+        "mixed_precision": variants,
         "cpu_baseline": cpu,
         "monitors": {"nonphys": mon["nonphys"], "min_alpha": mon["min_alpha"],
                      "max_alpha": mon["max_alpha"]},

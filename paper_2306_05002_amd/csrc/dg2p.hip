@@ -81,8 +81,8 @@ int check_params(const dg2p_mesh_s* m, const dg2p_params* p) {
   if (!(p->c_ip > 0.0)) return fail(DG2P_EINVAL, "c_ip must be > 0");
   if (!(p->grad_reg >= 0.0)) return fail(DG2P_EINVAL, "grad_reg must be >= 0");
   if (!std::isfinite(p->sigma)) return fail(DG2P_EINVAL, "sigma must be finite");
-  if (p->precision != DG2P_FP64)
-    return fail(DG2P_EUNSUPPORTED, "only DG2P_FP64 is available in this build");
+  if (p->precision < DG2P_FP64 || p->precision > DG2P_MIXED_BF16)
+    return fail(DG2P_EINVAL, "unknown precision");
   (void)m;
   return DG2P_OK;
 }
@@ -247,42 +247,55 @@ int check_ws(void* work, size_t need) {
 
 dim3 elem_grid(const KArgs& A) { return dim3((unsigned)(8 * A.xcd_chunk)); }
 
-template <int DIM, bool VISC>
-void launch_ingredients(const KArgs& A, const double* U, double* G, double* rec, hipStream_t s) {
+template <int DIM, bool VISC, int PR>
+void launch_ingredients_p(const KArgs& A, const double* U, double* G, double* rec, hipStream_t s) {
   TimedLaunch t(DG2P_K_INGREDIENTS, s);
-  hipLaunchKernelGGL((k_ingredients<DIM, VISC>), elem_grid(A), dim3(BLOCK), 0, s, A, U, G, rec);
+  hipLaunchKernelGGL((k_ingredients<DIM, VISC, PR>), elem_grid(A), dim3(BLOCK), 0, s, A, U, G, rec);
+}
+template <int DIM, bool VISC>
+void launch_ingredients(int prec, const KArgs& A, const double* U, double* G, double* rec, hipStream_t s) {
+  if (prec == DG2P_MIXED_FP32) launch_ingredients_p<DIM, VISC, 1>(A, U, G, rec, s);
+  else if (prec == DG2P_MIXED_BF16) launch_ingredients_p<DIM, VISC, 2>(A, U, G, rec, s);
+  else launch_ingredients_p<DIM, VISC, 0>(A, U, G, rec, s);
 }
 
-template <int DIM, bool VISC, bool CSF, bool DIRI>
-void launch_stage_t(int mode, int epi, const KArgs& A, const StageIO& io, hipStream_t s) {
+template <int DIM, bool VISC, bool CSF, bool DIRI, int PR>
+void launch_stage_p(int mode, int epi, const KArgs& A, const StageIO& io, hipStream_t s) {
   TimedLaunch t(DG2P_K_STAGE, s);
   const dim3 g = elem_grid(A), b(BLOCK);
   if (mode == 0)
-    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 0, 0>), g, b, 0, s, A, io);
+    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 0, 0, PR>), g, b, 0, s, A, io);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 1, 1>), g, b, 0, s, A, io);
+    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 1, 1, PR>), g, b, 0, s, A, io);
   else if (epi == 1)
-    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 2, 1>), g, b, 0, s, A, io);
+    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 2, 1, PR>), g, b, 0, s, A, io);
   else if (epi == 2)
-    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 2, 2>), g, b, 0, s, A, io);
+    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 2, 2, PR>), g, b, 0, s, A, io);
   else
-    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 2, 0>), g, b, 0, s, A, io);
+    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 2, 0, PR>), g, b, 0, s, A, io);
+}
+template <int DIM, bool VISC, bool CSF, bool DIRI>
+void launch_stage_t(int prec, int mode, int epi, const KArgs& A, const StageIO& io, hipStream_t s) {
+  if (prec == DG2P_MIXED_FP32) launch_stage_p<DIM, VISC, CSF, DIRI, 1>(mode, epi, A, io, s);
+  else if (prec == DG2P_MIXED_BF16) launch_stage_p<DIM, VISC, CSF, DIRI, 2>(mode, epi, A, io, s);
+  else launch_stage_p<DIM, VISC, CSF, DIRI, 0>(mode, epi, A, io, s);
 }
 
 template <int DIM>
 void launch_stage_d(const dg2p_mesh_s* m, const dg2p_params* p, int mode, int epi, const KArgs& A,
                     const StageIO& io, hipStream_t s) {
   const bool visc = viscous(p), csf = p->sigma != 0.0, diri = has_dirichlet(m);
+  const int pr = p->precision;
   if (diri) {
-    if (visc && csf) launch_stage_t<DIM, true, true, true>(mode, epi, A, io, s);
-    else if (visc) launch_stage_t<DIM, true, false, true>(mode, epi, A, io, s);
-    else if (csf) launch_stage_t<DIM, false, true, true>(mode, epi, A, io, s);
-    else launch_stage_t<DIM, false, false, true>(mode, epi, A, io, s);
+    if (visc && csf) launch_stage_t<DIM, true, true, true>(pr, mode, epi, A, io, s);
+    else if (visc) launch_stage_t<DIM, true, false, true>(pr, mode, epi, A, io, s);
+    else if (csf) launch_stage_t<DIM, false, true, true>(pr, mode, epi, A, io, s);
+    else launch_stage_t<DIM, false, false, true>(pr, mode, epi, A, io, s);
   } else {
-    if (visc && csf) launch_stage_t<DIM, true, true, false>(mode, epi, A, io, s);
-    else if (visc) launch_stage_t<DIM, true, false, false>(mode, epi, A, io, s);
-    else if (csf) launch_stage_t<DIM, false, true, false>(mode, epi, A, io, s);
-    else launch_stage_t<DIM, false, false, false>(mode, epi, A, io, s);
+    if (visc && csf) launch_stage_t<DIM, true, true, false>(pr, mode, epi, A, io, s);
+    else if (visc) launch_stage_t<DIM, true, false, false>(pr, mode, epi, A, io, s);
+    else if (csf) launch_stage_t<DIM, false, true, false>(pr, mode, epi, A, io, s);
+    else launch_stage_t<DIM, false, false, false>(pr, mode, epi, A, io, s);
   }
 }
 
@@ -298,10 +311,11 @@ void launch_stage(const dg2p_mesh_s* m, const dg2p_params* p, int mode, int epi,
 void launch_ingr(const dg2p_mesh_s* m, const dg2p_params* p, const KArgs& A, const double* U, double* G,
                  double* rec, hipStream_t s) {
   const bool v = viscous(p);
+  const int pr = p->precision;
   switch (m->dim) {
-    case 1: v ? launch_ingredients<1, true>(A, U, G, rec, s) : launch_ingredients<1, false>(A, U, G, rec, s); break;
-    case 2: v ? launch_ingredients<2, true>(A, U, G, rec, s) : launch_ingredients<2, false>(A, U, G, rec, s); break;
-    default: v ? launch_ingredients<3, true>(A, U, G, rec, s) : launch_ingredients<3, false>(A, U, G, rec, s); break;
+    case 1: v ? launch_ingredients<1, true>(pr, A, U, G, rec, s) : launch_ingredients<1, false>(pr, A, U, G, rec, s); break;
+    case 2: v ? launch_ingredients<2, true>(pr, A, U, G, rec, s) : launch_ingredients<2, false>(pr, A, U, G, rec, s); break;
+    default: v ? launch_ingredients<3, true>(pr, A, U, G, rec, s) : launch_ingredients<3, false>(pr, A, U, G, rec, s); break;
   }
 }
 

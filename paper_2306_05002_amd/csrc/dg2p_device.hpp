@@ -206,6 +206,95 @@ __device__ __forceinline__ double dk(double f, int k, const LaneD<DIM>& L, const
   return 0.0;
 }
 
+// ---- mixed-precision contractions -------------------------------------------
+// Inputs are the fluctuation f - f_ref about the element's value at its node 0
+// (formed in FP64; D annihilates constants, so the result is the same
+// derivative and a uniform field contracts to exactly zero), rounded to FP32
+// (PR = 1) or to BF16 (PR = 2, coefficients rounded too), moved with 32-bit
+// lane exchanges and accumulated in FP32.
+template <int CTRL>
+__device__ __forceinline__ float dpp32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float bf16_round(float x) {
+  unsigned u = __float_as_uint(x);
+  u = (u + (((u >> 16) & 1u) + 0x7FFFu)) & 0xFFFF0000u;  // round to nearest even
+  return __uint_as_float(u);
+}
+template <int DIM>
+__device__ __forceinline__ double elem_ref(double f) {
+  constexpr int NN = 1 << (2 * DIM);
+  return __shfl(f, __lane_id() & ~(NN - 1));
+}
+template <int DIM>
+struct LaneF {
+  float c[DIM][4];
+};
+template <int DIM, int PR>
+__device__ __forceinline__ void lane_coeffs_f(const int* ak, LaneF<DIM>& L) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    float x = (float)sel4(ak[0], CX(0, r), CX(1, r), CX(2, r), CX(3, r));
+    L.c[0][r] = PR == 2 ? bf16_round(x) : x;
+    if constexpr (DIM > 1) {
+      float y = (float)sel4(ak[1], CY(0, r), CY(1, r), CY(2, r), CY(3, r));
+      L.c[1][r] = PR == 2 ? bf16_round(y) : y;
+    }
+    if constexpr (DIM > 2) {
+      float z = (float)sel4(ak[2], CZ(0, r), CZ(1, r), CZ(2, r), CZ(3, r));
+      L.c[2][r] = PR == 2 ? bf16_round(z) : z;
+    }
+  }
+}
+template <int K, int DIM>
+__device__ __forceinline__ float contract_f(float d, const LaneF<DIM>& L) {
+  const float* c = L.c[K];
+  if constexpr (K == 0) {
+    float r = c[0] * d;
+    r = fmaf(c[1], dpp32<0x39>(d), r);   // quad rotation by 1
+    r = fmaf(c[2], dpp32<0x4E>(d), r);   // by 2
+    return fmaf(c[3], dpp32<0x93>(d), r);  // by 3
+  } else if constexpr (K == 1) {
+    float r = c[0] * d;
+    r = fmaf(c[1], dpp32<0x124>(d), r);  // row rotation by 4
+    r = fmaf(c[2], dpp32<0x128>(d), r);  // by 8
+    return fmaf(c[3], dpp32<0x12C>(d), r);  // by 12
+  } else {
+    float r = c[0] * d;
+    r = fmaf(c[1], __shfl_xor(d, 16), r);
+    r = fmaf(c[2], __shfl_xor(d, 32), r);
+    return fmaf(c[3], __shfl_xor(d, 48), r);
+  }
+}
+
+// Derivative along axis k in the precision PR (0: FP64, 1: FP32, 2: BF16 inputs).
+template <int DIM, int PR>
+struct Deriv {
+  LaneD<DIM> L;
+  LaneF<DIM> F;
+};
+template <int DIM, int PR>
+__device__ __forceinline__ double dkp(double f, int k, const Deriv<DIM, PR>& Dv, const KArgs& A) {
+  if constexpr (PR == 0) {
+    return dk<DIM>(f, k, Dv.L, A);
+  } else {
+    float d = (float)(f - elem_ref<DIM>(f));
+    if constexpr (PR == 2) d = bf16_round(d);
+    float r;
+    if (k == 0) r = contract_f<0, DIM>(d, Dv.F);
+    else if (DIM > 1 && k == 1) r = contract_f<(DIM > 1 ? 1 : 0), DIM>(d, Dv.F);
+    else r = contract_f<(DIM > 2 ? 2 : 0), DIM>(d, Dv.F);
+    return (double)r * A.Jinv[k];
+  }
+}
+template <int DIM, int PR>
+__device__ __forceinline__ void deriv_setup(const KArgs& A, const int* ak, Deriv<DIM, PR>& Dv) {
+  if constexpr (PR == 0)
+    lane_coeffs<DIM>(A, ak, Dv.L);
+  else
+    lane_coeffs_f<DIM, PR>(ak, Dv.F);
+}
+
 // Value of f at the low (a_k = 0) / high (a_k = 3) end of the lane's line along k.
 template <int K>
 __device__ __forceinline__ double line_end(double f, int ak_k, bool high) {
@@ -280,9 +369,9 @@ struct Grad {
   double mu;
 };
 
-template <int DIM, bool VISC>
+template <int DIM, bool VISC, int PR>
 __device__ __forceinline__ void gradients(const KArgs& A, const double* q, const Prim& p,
-                                          const LaneD<DIM>& L, Grad<DIM, VISC>& g) {
+                                          const Deriv<DIM, PR>& L, Grad<DIM, VISC>& g) {
   const double al = q[3 + DIM];
   const double ps = q[4 + DIM];
   double gP[DIM];
@@ -290,8 +379,8 @@ __device__ __forceinline__ void gradients(const KArgs& A, const double* q, const
   g.upsi = 0.0;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
-    g.gA[k] = dk<DIM>(al, k, L, A);
-    gP[k] = dk<DIM>(ps, k, L, A);
+    g.gA[k] = dkp<DIM, PR>(al, k, L, A);
+    gP[k] = dkp<DIM, PR>(ps, k, L, A);
     g2 = fma(gP[k], gP[k], g2);
     g.upsi = fma(p.u[k], gP[k], g.upsi);
   }
@@ -307,7 +396,7 @@ __device__ __forceinline__ void gradients(const KArgs& A, const double* q, const
 #pragma unroll
     for (int j = 0; j < DIM; ++j)
 #pragma unroll
-      for (int k = 0; k < DIM; ++k) gU[j][k] = dk<DIM>(p.u[j], k, L, A);
+      for (int k = 0; k < DIM; ++k) gU[j][k] = dkp<DIM, PR>(p.u[j], k, L, A);
     double div = 0.0;
 #pragma unroll
     for (int j = 0; j < DIM; ++j) div += gU[j][j];
@@ -469,9 +558,9 @@ __device__ __forceinline__ long long logical_block(const KArgs& A) {
 }
 
 // ---- epilogue: face ingredients and records of a state held per lane ----------------
-template <int DIM, bool VISC, bool WRITE_G, bool WRITE_REC>
+template <int DIM, bool VISC, bool WRITE_G, bool WRITE_REC, int PR>
 __device__ __forceinline__ void emit(const KArgs& A, const double* q, long long e, bool valid, int node,
-                                     const int* ak, const LaneD<DIM>& L, double* G, double* rec,
+                                     const int* ak, const Deriv<DIM, PR>& L, double* G, double* rec,
                                      long long blk) {
   constexpr int NN = 1 << (2 * DIM);
   constexpr int NFN = NN / 4;
@@ -480,7 +569,7 @@ __device__ __forceinline__ void emit(const KArgs& A, const double* q, long long 
   closure<DIM>(A, q, p);
   if constexpr (WRITE_G) {
     Grad<DIM, VISC> g;
-    gradients<DIM, VISC>(A, q, p, L, g);
+    gradients<DIM, VISC, PR>(A, q, p, L, g);
     if (valid) {
 #pragma unroll
       for (int k = 0; k < DIM; ++k) {
@@ -505,7 +594,7 @@ __device__ __forceinline__ void emit(const KArgs& A, const double* q, long long 
 
 // ---------------------------------------------------------------------------
 // Ingredient pass: G and records of a state (first stage of a step, residual).
-template <int DIM, bool VISC>
+template <int DIM, bool VISC, int PR>
 __global__ __launch_bounds__(BLOCK) void k_ingredients(KArgs A, const double* __restrict__ U,
                                                        double* __restrict__ G, double* __restrict__ rec) {
   constexpr int NN = 1 << (2 * DIM);
@@ -521,12 +610,12 @@ __global__ __launch_bounds__(BLOCK) void k_ingredients(KArgs A, const double* __
   int ak[3] = {0, 0, 0};
 #pragma unroll
   for (int k = 0; k < DIM; ++k) ak[k] = (node >> (2 * k)) & 3;
-  LaneD<DIM> L;
-  lane_coeffs<DIM>(A, ak, L);
+  Deriv<DIM, PR> L;
+  deriv_setup<DIM, PR>(A, ak, L);
   double q[NF];
 #pragma unroll
   for (int f = 0; f < NF; ++f) q[f] = U[(f * A.E + e) * NN + node];
-  emit<DIM, VISC, true, true>(A, q, e, valid, node, ak, L, G, rec, blk);
+  emit<DIM, VISC, true, true, PR>(A, q, e, valid, node, ak, L, G, rec, blk);
 }
 
 // ---------------------------------------------------------------------------
@@ -534,7 +623,7 @@ __global__ __launch_bounds__(BLOCK) void k_ingredients(KArgs A, const double* __
 // symmetric term), then MODE 0: store R; MODE 1: U_out = U_s + dt R;
 // MODE 2: U_out = rk_a U_n + rk_b (U_s + dt R).  Epilogue on U_out: EPI = 1
 // face ingredients into Gout, EPI = 2 also the reduction records.
-template <int DIM, bool VISC, bool CSF, bool DIRI, int MODE, int EPI>
+template <int DIM, bool VISC, bool CSF, bool DIRI, int MODE, int EPI, int PR>
 __global__ __launch_bounds__(BLOCK) void k_stage(KArgs A, StageIO io) {
   constexpr int NN = 1 << (2 * DIM);
   constexpr int EPW = 64 / NN;
@@ -552,8 +641,8 @@ __global__ __launch_bounds__(BLOCK) void k_stage(KArgs A, StageIO io) {
   int ak[3] = {0, 0, 0};
 #pragma unroll
   for (int k = 0; k < DIM; ++k) ak[k] = (node >> (2 * k)) & 3;
-  LaneD<DIM> L;
-  lane_coeffs<DIM>(A, ak, L);
+  Deriv<DIM, PR> L;
+  deriv_setup<DIM, PR>(A, ak, L);
 
   const double* __restrict__ Us = io.Us;
   double q[NF];
@@ -562,7 +651,7 @@ __global__ __launch_bounds__(BLOCK) void k_stage(KArgs A, StageIO io) {
   Prim pr;
   closure<DIM>(A, q, pr);
   Grad<DIM, VISC> g;
-  gradients<DIM, VISC>(A, q, pr, L, g);
+  gradients<DIM, VISC, PR>(A, q, pr, L, g);
 
   double R[NF];
   // volume terms, strong form: R_q = sum_k (1/J_k) D_k (-F_q + s_q a + V_q)_k
@@ -583,7 +672,7 @@ __global__ __launch_bounds__(BLOCK) void k_stage(KArgs A, StageIO io) {
           fl = fma(g.mu, tu, fl);
         }
       }
-      acc += dk<DIM>(fl, k, L, A);
+      acc += dkp<DIM, PR>(fl, k, L, A);
     }
     R[qi] = acc;
   }
@@ -591,7 +680,7 @@ __global__ __launch_bounds__(BLOCK) void k_stage(KArgs A, StageIO io) {
     double acc = 0.0, ua = 0.0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-      acc += dk<DIM>(g.a[k], k, L, A);
+      acc += dkp<DIM, PR>(g.a[k], k, L, A);
       ua = fma(pr.u[k], g.gA[k], ua);
     }
     R[3 + DIM] = acc - ua;  // div a, and transport as a volume source
@@ -604,7 +693,7 @@ __global__ __launch_bounds__(BLOCK) void k_stage(KArgs A, StageIO io) {
       double div = 0.0, ga2 = 0.0;
 #pragma unroll
       for (int k = 0; k < DIM; ++k) {
-        div += dk<DIM>(g.nh[k], k, L, A);
+        div += dkp<DIM, PR>(g.nh[k], k, L, A);
         ga2 = fma(g.gA[k], g.gA[k], ga2);
       }
       const double kappa = -div;
@@ -807,7 +896,7 @@ __global__ __launch_bounds__(BLOCK) void k_stage(KArgs A, StageIO io) {
 #pragma unroll
       for (int f = 0; f < NF; ++f) io.Out[f * fs + o] = uo[f];
     }
-    if constexpr (EPI > 0) emit<DIM, VISC, true, (EPI > 1)>(A, uo, e, valid, node, ak, L, io.Gout, io.rec, blk);
+    if constexpr (EPI > 0) emit<DIM, VISC, true, (EPI > 1), PR>(A, uo, e, valid, node, ak, L, io.Gout, io.rec, blk);
   }
 }
 

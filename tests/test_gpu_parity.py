@@ -232,6 +232,46 @@ def test_advance_fixed_dt():
     assert max(state_errors(A.cpu(), Uo, prm, om.d)) <= 1e-12
 
 
+# ---- mixed precision: error vs the FP64 oracle, stated per field -------------------
+# A-priori bound per contraction (the standard dot-product rounding bound,
+# inputs rounded once): |err| <= (n + 1) u sum_b |D_ab| |f_b - f_ref| / J with
+# n = 4 terms, sum_b |D_ab| <= 9.1, J = h / 2, u = 2^-24 (FP32) or 2^-8
+# (BF16; coefficients rounded too).  With |f - f_ref| <= 2 max|F| and
+# max|F| bounded by the parity scale S_f times h, one contraction is within
+# 5 u 9.1 * 2 * 2 = 182 u of S_f, and a residual component sums d of them:
+# 3.3e-5 for FP32 (d = 3) and O(1) for BF16 -- the bars below.
+MIXED = [("drop2d", (9, 7)), ("shock2d", (12, 6)), ("adjoint2d", (8, 7)), ("rt3d", (3, 4, 3)),
+         ("drop1d", (19,))]
+
+
+@pytest.mark.parametrize("prec,bar", [("fp32", 3.3e-5), ("bf16", 2.2)])
+@pytest.mark.parametrize("name,ne", MIXED)
+def test_mixed_precision_rhs_error(name, ne, prec, bar):
+    cfg, om, prm, U0, mesh, P = gpu_case(name, ne)
+    dg = _dg()
+    Pm = dg.make_params(cfg["params"], precision=prec)
+    Ro = oracle.rhs(U0, om, prm)
+    Rm = dg.rhs(mesh, Pm, U0.cuda().contiguous()).cpu()
+    errs = res_errors(Rm, Ro, U0, oracle.max_rate(U0, om, prm), prm, om.d)
+    print(name, prec, ["%.2e" % e for e in errs])
+    assert max(errs) <= bar, errs
+    if prec == "fp32":
+        assert max(errs) > 0.0   # it really is a different (lower) precision path
+
+
+def test_mixed_precision_interface_equilibrium():
+    """Uniform P and u contract to exactly zero in the fluctuation form; the
+    remaining drift comes from FP32 rounding of the varying fluxes."""
+    cfg, om, prm, U0, mesh, P = gpu_case("drop2d", (16, 16))
+    dg = _dg()
+    Pm = dg.make_params(cfg["params"], precision="fp32")
+    U = U0.cuda().contiguous()
+    dg.advance(mesh, Pm, U, 50)
+    m = dg.monitors(mesh, Pm, U, p_ref=1.0, u_ref=[1.0, 0.5])
+    print("fp32 IEC after 50 steps", m["dev_p"], m["dev_u"])
+    assert m["dev_p"] < 1e-5 and m["dev_u"] < 1e-5 and m["nonphys"] == 0
+
+
 FULL = ["drop2d", "shock2d", "adjoint2d", "rt3d"]
 
 
