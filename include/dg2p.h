@@ -144,6 +144,10 @@ int dg2p_layout(dg2p_mesh m, int* n_fields, long long* n_elem, int* nodes_per_el
 /* Physical GLL node coordinates, host array xyz[d][E][4^d] (caller-owned). */
 int dg2p_node_coords(dg2p_mesh m, double* xyz /*host*/);
 
+/* Diagonal mass-matrix weights W_j = prod_k w_{a_k} J_k of the 4^d nodes of
+ * an element (identical for every element), host array W[4^d]. */
+int dg2p_node_weights(dg2p_mesh m, double* W /*host*/);
+
 /* Bytes of device workspace that `op` needs for this mesh and parameters. */
 int dg2p_workspace_size(dg2p_mesh m, const dg2p_params* p /*host*/, int op, size_t* bytes /*host*/);
 
@@ -152,6 +156,12 @@ int dg2p_workspace_size(dg2p_mesh m, const dg2p_params* p /*host*/, int op, size
  * prim, U: device arrays [N_f][E][4^d] (layouts above); may not alias. */
 int dg2p_prim_to_cons(dg2p_mesh m, const dg2p_params* p /*host*/, const double* prim /*device*/,
                       double* U /*device*/, void* stream);
+
+/* Reverse of dg2p_prim_to_cons: prim_bar = (dU/dprim)^T U_bar, all primitive
+ * fields (alpha, psi, rho_1, rho_2, u, P), overwritten.  Device arrays
+ * [N_f][E][4^d], no aliasing. */
+int dg2p_prim_to_cons_vjp(dg2p_mesh m, const dg2p_params* p /*host*/, const double* prim /*device*/,
+                          const double* U_bar /*device*/, double* prim_bar /*device, out*/, void* stream);
 
 /* Semi-discrete residual R = dU/dt (mass matrix already inverted): volume
  * terms in strong form (equal to the paper's weak form under GLL
@@ -187,6 +197,26 @@ int dg2p_advance(dg2p_mesh m, const dg2p_params* p /*host*/, double* U /*device,
                  double* dt_last /*device, nullable*/, dg2p_monitors* mon /*device, nullable*/,
                  double p_ref, const double* u_ref /*host, nullable*/, void* work /*device*/, void* stream);
 
+/* Vector-Jacobian product of dg2p_rhs (hand-written reverse mode):
+ * U_bar = (dR/dU)^T R_bar, overwritten; if param_bar != NULL,
+ * param_bar[0] += <R_bar, dR/dsigma> (surface tension).  Non-smooth points:
+ * d max(a,b) splits 1/2, 1/2 at ties, d|x|/dx = 0 at 0.  FP64 and periodic
+ * meshes only (DG2P_EUNSUPPORTED otherwise).  U, R_bar, U_bar: device
+ * [N_f][E][4^d]; U_bar may not alias.  work: DG2P_OP_RHS_VJP bytes. */
+int dg2p_rhs_vjp(dg2p_mesh m, const dg2p_params* p /*host*/, const double* U /*device*/,
+                 const double* R_bar /*device*/, double* U_bar /*device, out*/,
+                 double* param_bar /*device, nullable, accumulated*/, void* work /*device*/, void* stream);
+
+/* Vector-Jacobian product of one dg2p_rk_step with the (frozen) step *dt:
+ * U_n_bar = (dU_{n+1}/dU_n)^T U_np1_bar (overwritten), param_bar[0] +=
+ * <U_np1_bar, dU_{n+1}/dsigma>.  Recomputes the two intermediate stages from
+ * U_n, then reverses the three stages (three dg2p_rhs_vjp).  Same
+ * restrictions as dg2p_rhs_vjp.  work: DG2P_OP_RK_STEP_VJP bytes. */
+int dg2p_rk_step_vjp(dg2p_mesh m, const dg2p_params* p /*host*/, const double* U_n /*device*/,
+                     const double* dt /*device*/, const double* U_np1_bar /*device*/,
+                     double* U_n_bar /*device, out*/, double* param_bar /*device, nullable*/,
+                     void* work /*device*/, void* stream);
+
 /* Monitors of a state (all fields of *mon; dt is set to 0.1 / max_rate).  p_ref and u_ref are
  * the reference pressure and velocity of dev_p / dev_u (host values).
  * work: DG2P_OP_MONITORS bytes.  Deterministic (fixed reduction order). */
@@ -201,7 +231,9 @@ typedef enum {
   DG2P_K_RATE = 2,        /* time-step rate reduction, first pass */
   DG2P_K_RATE_FINAL = 3,  /* time-step rate reduction, final pass */
   DG2P_K_MONITOR = 4,     /* monitor reduction */
-  DG2P_K_PRIM = 5         /* initial-condition map */
+  DG2P_K_PRIM = 5,        /* initial-condition map */
+  DG2P_K_VJP_LOCAL = 6,   /* adjoint: own-element reverse pass */
+  DG2P_K_VJP_GATHER = 7   /* adjoint: neighbour-contribution gather pass */
 } dg2p_kernel_kind;
 
 /* Benchmark timing.  While enabled, every kernel the library launches is

@@ -37,9 +37,10 @@ from .mesh import OracleMesh
 from .physics import Params, primitives, prim_to_cons
 from .residual import rhs
 from .stepper import max_rate, max_dt, rk_step, monitors
+from . import adjoint
 
 __all__ = [
     "gll_nodes_weights", "derivative_matrix", "OracleMesh", "Params",
     "primitives", "prim_to_cons", "rhs", "max_rate", "max_dt", "rk_step",
-    "monitors",
+    "monitors", "adjoint",
 ]

@@ -244,7 +244,7 @@ def _rhs_batch(U, mesh, prm, el):
     # sources: gravity and continuum surface force
     rho = own["pr"]["rho"]
     nhat = own["nhat"]
-    if prm.sigma != 0.0:
+    if torch.is_tensor(prm.sigma) or prm.sigma != 0.0:
         kappa = -sum(_dk(nhat[k], k, mesh) for k in range(d))
         delta = prm.grad_reg
         dG = torch.sqrt((raw["gA"] * raw["gA"]).sum(0) + delta * delta) - delta

@@ -13,6 +13,7 @@
 
 #include "../../include/dg2p.h"
 #include "dg2p_device.hpp"
+#include "dg2p_adjoint.hpp"
 
 using namespace dg2p;
 
@@ -202,8 +203,17 @@ struct Work {
   double* dt = nullptr;  // internal device scalar
 };
 
+size_t fb_bytes(const dg2p_mesh_s* m, const dg2p_params* p) {
+  const int C = viscous(p) ? 1 + m->dim : 1;
+  return align256(sizeof(double) * (size_t)(2 * m->dim) * (m->nf + C) * (size_t)m->E * m->nfn);
+}
+size_t vjp_rec_bytes(const dg2p_mesh_s* m) { return align256(sizeof(double) * (size_t)(elem_blocks(m) + 1)); }
+
 size_t work_bytes(const dg2p_mesh_s* m, const dg2p_params* p, int op) {
   switch (op) {
+    case DG2P_OP_RHS_VJP: return g_bytes(m, p) + state_bytes(m) + fb_bytes(m, p) + vjp_rec_bytes(m);
+    case DG2P_OP_RK_STEP_VJP:
+      return 3 * g_bytes(m, p) + 5 * state_bytes(m) + fb_bytes(m, p) + vjp_rec_bytes(m) + rec_bytes(m);
     case DG2P_OP_RHS: return g_bytes(m, p) + rec_bytes(m);
     case DG2P_OP_RK_STEP: return 2 * g_bytes(m, p) + 2 * state_bytes(m) + rec_bytes(m);
     case DG2P_OP_ADVANCE: return 2 * g_bytes(m, p) + 2 * state_bytes(m) + rec_bytes(m) + 256;
@@ -368,6 +378,45 @@ void finalize(const dg2p_mesh_s* m, const KArgs& A, const Work& w, long long n, 
                      dt_fixed, dt, t, mon);
 }
 
+bool all_periodic(const dg2p_mesh_s* m) {
+  for (int k = 0; k < m->dim; ++k)
+    if (m->desc.bc[k][0] != DG2P_BC_PERIODIC) return false;
+  return true;
+}
+
+template <int DIM, bool VISC, bool CSF>
+void launch_vjp_d(const KArgs& A, const VjpIO& io, hipStream_t s) {
+  {
+    TimedLaunch t(DG2P_K_VJP_LOCAL, s);
+    hipLaunchKernelGGL((k_vjp_local<DIM, VISC, CSF>), elem_grid(A), dim3(BLOCK), 0, s, A, io);
+  }
+  TimedLaunch t(DG2P_K_VJP_GATHER, s);
+  hipLaunchKernelGGL((k_vjp_gather<DIM, VISC>), elem_grid(A), dim3(BLOCK), 0, s, A, io);
+}
+
+template <int DIM>
+void launch_vjp_dim(bool visc, bool csf, const KArgs& A, const VjpIO& io, hipStream_t s) {
+  if (visc && csf) launch_vjp_d<DIM, true, true>(A, io, s);
+  else if (visc) launch_vjp_d<DIM, true, false>(A, io, s);
+  else if (csf) launch_vjp_d<DIM, false, true>(A, io, s);
+  else launch_vjp_d<DIM, false, false>(A, io, s);
+}
+
+// Ub (+)= (dR/dU)^T Rb at state U; sigma cotangent added to *sigb when non-NULL.
+void residual_vjp(const dg2p_mesh_s* m, const dg2p_params* p, const KArgs& A, const double* U, const double* G,
+                  const double* Rb, double* T, double* FB, double* rec, double* Ub, int accumulate, double* sigb,
+                  hipStream_t s) {
+  const bool visc = viscous(p);
+  const bool csf = p->sigma != 0.0 || sigb != nullptr;
+  VjpIO io{U, G, Rb, T, FB, rec, Ub, accumulate};
+  switch (m->dim) {
+    case 1: launch_vjp_dim<1>(visc, csf, A, io, s); break;
+    case 2: launch_vjp_dim<2>(visc, csf, A, io, s); break;
+    default: launch_vjp_dim<3>(visc, csf, A, io, s); break;
+  }
+  if (sigb && csf) hipLaunchKernelGGL(k_sum_add, dim3(1), dim3(BLOCK), 0, s, rec, A.nblocks, sigb);
+}
+
 }  // namespace
 
 extern "C" {
@@ -466,8 +515,10 @@ int dg2p_workspace_size(dg2p_mesh m, const dg2p_params* p, int op, size_t* bytes
     case DG2P_OP_RK_STEP:
     case DG2P_OP_ADVANCE:
     case DG2P_OP_MAX_DT:
-    case DG2P_OP_MONITORS: *bytes = work_bytes(m, p, op); break;
-    default: return fail(DG2P_EUNSUPPORTED, "operation not available in this build");
+    case DG2P_OP_MONITORS:
+    case DG2P_OP_RHS_VJP:
+    case DG2P_OP_RK_STEP_VJP: *bytes = work_bytes(m, p, op); break;
+    default: return fail(DG2P_EINVAL, "unknown operation");
   }
   return DG2P_OK;
 }
@@ -489,6 +540,35 @@ int dg2p_prim_to_cons(dg2p_mesh m, const dg2p_params* p, const double* prim, dou
     default: hipLaunchKernelGGL((k_prim_to_cons<3>), dim3(blocks), dim3(256), 0, s, A, prim, U, n); break;
   }
   return hip_check(hipGetLastError(), "prim_to_cons launch");
+}
+
+int dg2p_prim_to_cons_vjp(dg2p_mesh m, const dg2p_params* p, const double* prim, const double* U_bar,
+                          double* prim_bar, void* stream) {
+  g_last_error.clear();
+  if (!m || !prim || !U_bar || !prim_bar) return fail(DG2P_EINVAL, "mesh, prim, U_bar and prim_bar must be non-NULL");
+  if (prim_bar == prim || prim_bar == U_bar) return fail(DG2P_EINVAL, "prim_bar may not alias");
+  int st = check_params(m, p);
+  if (st) return st;
+  KArgs A = make_args(m, p);
+  const long long n = m->E * m->nn;
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  hipStream_t s = (hipStream_t)stream;
+  switch (m->dim) {
+    case 1: hipLaunchKernelGGL((k_prim_to_cons_vjp<1>), dim3(blocks), dim3(256), 0, s, A, prim, U_bar, prim_bar, n); break;
+    case 2: hipLaunchKernelGGL((k_prim_to_cons_vjp<2>), dim3(blocks), dim3(256), 0, s, A, prim, U_bar, prim_bar, n); break;
+    default: hipLaunchKernelGGL((k_prim_to_cons_vjp<3>), dim3(blocks), dim3(256), 0, s, A, prim, U_bar, prim_bar, n); break;
+  }
+  return hip_check(hipGetLastError(), "prim_to_cons_vjp launch");
+}
+
+int dg2p_node_weights(dg2p_mesh m, double* W) {
+  if (!m || !W) return fail(DG2P_EINVAL, "mesh and W must be non-NULL");
+  for (int j = 0; j < m->nn; ++j) {
+    double w = 1.0;
+    for (int k = 0; k < m->dim; ++k) w *= m->w[(j >> (2 * k)) & 3] * m->J[k];
+    W[j] = w;
+  }
+  return DG2P_OK;
 }
 
 int dg2p_rhs(dg2p_mesh m, const dg2p_params* p, const double* U, double* R, void* work, void* stream) {
@@ -612,6 +692,86 @@ int dg2p_compute_monitors(dg2p_mesh m, const dg2p_params* p, const double* U, do
   launch_records(m, p, A, U, w.rec, s);
   finalize(m, A, w, records_of_records(m, p, 1), 0.1, nullptr, nullptr, nullptr, mon, s);
   return hip_check(hipGetLastError(), "monitor launch");
+}
+
+int dg2p_rhs_vjp(dg2p_mesh m, const dg2p_params* p, const double* U, const double* R_bar, double* U_bar,
+                 double* param_bar, void* work, void* stream) {
+  g_last_error.clear();
+  if (!m || !U || !R_bar || !U_bar) return fail(DG2P_EINVAL, "mesh, U, R_bar and U_bar must be non-NULL");
+  if (U_bar == U || U_bar == R_bar) return fail(DG2P_EINVAL, "U_bar may not alias U or R_bar");
+  int st = check_params(m, p);
+  if (st) return st;
+  if (p->precision != DG2P_FP64) return fail(DG2P_EUNSUPPORTED, "the adjoint is FP64 only");
+  if (!all_periodic(m)) return fail(DG2P_EUNSUPPORTED, "the adjoint supports periodic meshes only");
+  st = check_ws(work, work_bytes(m, p, DG2P_OP_RHS_VJP));
+  if (st) return st;
+  KArgs A = make_args(m, p);
+  char* c = static_cast<char*>(work);
+  double* G = reinterpret_cast<double*>(c);
+  c += g_bytes(m, p);
+  double* T = reinterpret_cast<double*>(c);
+  c += state_bytes(m);
+  double* FB = reinterpret_cast<double*>(c);
+  c += fb_bytes(m, p);
+  double* rec = reinterpret_cast<double*>(c);
+  hipStream_t s = (hipStream_t)stream;
+  // forward face ingredients of U (the neighbours' a.e_k, tau.e_k); its records go to rec2-less scratch: T
+  launch_ingr(m, p, A, U, G, T, s);
+  residual_vjp(m, p, A, U, G, R_bar, T, FB, rec, U_bar, 0, param_bar, s);
+  return hip_check(hipGetLastError(), "rhs_vjp launch");
+}
+
+int dg2p_rk_step_vjp(dg2p_mesh m, const dg2p_params* p, const double* U_n, const double* dt, const double* U_np1_bar,
+                     double* U_n_bar, double* param_bar, void* work, void* stream) {
+  g_last_error.clear();
+  if (!m || !U_n || !dt || !U_np1_bar || !U_n_bar)
+    return fail(DG2P_EINVAL, "mesh, U_n, dt, U_np1_bar and U_n_bar must be non-NULL");
+  if (U_n_bar == U_n || U_n_bar == U_np1_bar) return fail(DG2P_EINVAL, "U_n_bar may not alias U_n or U_np1_bar");
+  int st = check_params(m, p);
+  if (st) return st;
+  if (p->precision != DG2P_FP64) return fail(DG2P_EUNSUPPORTED, "the adjoint is FP64 only");
+  if (!all_periodic(m)) return fail(DG2P_EUNSUPPORTED, "the adjoint supports periodic meshes only");
+  st = check_ws(work, work_bytes(m, p, DG2P_OP_RK_STEP_VJP));
+  if (st) return st;
+  KArgs A = make_args(m, p);
+  const size_t gb = g_bytes(m, p), sb = state_bytes(m);
+  char* c = static_cast<char*>(work);
+  double* GA = reinterpret_cast<double*>(c); c += gb;
+  double* GB = reinterpret_cast<double*>(c); c += gb;
+  double* GC = reinterpret_cast<double*>(c); c += gb;
+  double* U1 = reinterpret_cast<double*>(c); c += sb;
+  double* U2 = reinterpret_cast<double*>(c); c += sb;
+  double* B = reinterpret_cast<double*>(c); c += sb;
+  double* Rb = reinterpret_cast<double*>(c); c += sb;
+  double* T = reinterpret_cast<double*>(c); c += sb;
+  double* FB = reinterpret_cast<double*>(c); c += fb_bytes(m, p);
+  double* rec = reinterpret_cast<double*>(c); c += vjp_rec_bytes(m);
+  double* rec2 = reinterpret_cast<double*>(c);
+  hipStream_t s = (hipStream_t)stream;
+  // forward recomputation: U1, U2 and the face ingredients of U_n, U1, U2
+  launch_ingr(m, p, A, U_n, GA, rec2, s);
+  {
+    StageIO io1{U_n, GA, nullptr, U1, GB, nullptr, dt};
+    launch_stage(m, p, 1, 1, A, io1, s);
+    KArgs B2 = A;
+    B2.rk_a = 0.75;
+    B2.rk_b = 0.25;
+    StageIO io2{U1, GB, U_n, U2, GC, nullptr, dt};
+    launch_stage(m, p, 2, 1, B2, io2, s);
+  }
+  const long long n = (long long)m->nf * m->E * m->nn;
+  const unsigned eb = (unsigned)((n + 255) / 256);
+  // U3 = 1/3 U + 2/3 (U2 + dt R(U2))
+  hipLaunchKernelGGL(k_vjp_combine, dim3(eb), dim3(256), 0, s, n, U_np1_bar, dt, 1.0 / 3.0, 1, U_n_bar, 2.0 / 3.0, B,
+                     2.0 / 3.0, Rb);
+  residual_vjp(m, p, A, U2, GC, Rb, T, FB, rec, B, 1, param_bar, s);
+  // U2 = 3/4 U + 1/4 (U1 + dt R(U1))
+  hipLaunchKernelGGL(k_vjp_combine, dim3(eb), dim3(256), 0, s, n, B, dt, 0.75, 0, U_n_bar, 0.25, B, 0.25, Rb);
+  residual_vjp(m, p, A, U1, GB, Rb, T, FB, rec, B, 1, param_bar, s);
+  // U1 = U + dt R(U)
+  hipLaunchKernelGGL(k_vjp_combine, dim3(eb), dim3(256), 0, s, n, B, dt, 1.0, 0, U_n_bar, 0.0, nullptr, 1.0, Rb);
+  residual_vjp(m, p, A, U_n, GA, Rb, T, FB, rec, U_n_bar, 1, param_bar, s);
+  return hip_check(hipGetLastError(), "rk_step_vjp launch");
 }
 
 int dg2p_timing_enable(int on) {

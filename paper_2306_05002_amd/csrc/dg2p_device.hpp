@@ -927,6 +927,41 @@ __global__ void k_prim_to_cons(KArgs A, const double* __restrict__ P, double* __
   U[(4 + DIM) * n + i] = ps;
 }
 
+// Reverse of the initial-condition map: primitive cotangents from U_bar.
+template <int DIM>
+__global__ void k_prim_to_cons_vjp(KArgs A, const double* __restrict__ P, const double* __restrict__ Ub,
+                                   double* __restrict__ Pb, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double al = P[0 * n + i], r1 = P[2 * n + i], r2 = P[3 * n + i];
+  const double p = P[(4 + DIM) * n + i];
+  const double rho = al * r1 + (1.0 - al) * r2;
+  const double xi = al * A.xi1 + (1.0 - al) * A.xi2;
+  double k2 = 0.0;
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) {
+    const double u = P[(4 + j) * n + i];
+    k2 = fma(u, u, k2);
+  }
+  const double Eb = Ub[(2 + DIM) * n + i];
+  // rho E = xi P + Pi + rho k
+  double rhob = 0.5 * k2 * Eb;
+  const double xib = p * Eb, pib = Eb;
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) {
+    const double u = P[(4 + j) * n + i];
+    const double mb = Ub[(2 + j) * n + i];
+    rhob += u * mb;
+    Pb[(4 + j) * n + i] = rho * mb + rho * u * Eb;
+  }
+  Pb[(4 + DIM) * n + i] = xi * Eb;
+  const double q1b = Ub[0 * n + i] + rhob, q2b = Ub[1 * n + i] + rhob;
+  Pb[0 * n + i] = r1 * q1b - r2 * q2b + (A.xi1 - A.xi2) * xib + (A.pi1 - A.pi2) * pib + Ub[(3 + DIM) * n + i];
+  Pb[1 * n + i] = Ub[(4 + DIM) * n + i];
+  Pb[2 * n + i] = al * q1b;
+  Pb[3 * n + i] = (1.0 - al) * q2b;
+}
+
 // ---------------------------------------------------------------------------
 // Records of a state without face ingredients (dt / monitor requests):
 // grid-stride over nodes, fixed grid.

@@ -69,10 +69,14 @@ _SIG = {
     "dg2p_rk_step": ([_vp, ctypes.POINTER(Params), _dp, _dp, _vp, _vp], _i),
     "dg2p_compute_monitors": ([_vp, ctypes.POINTER(Params), _dp, _d, _dp, _vp, _vp, _vp], _i),
     "dg2p_advance": ([_vp, ctypes.POINTER(Params), _dp, _i, _d, _dp, _dp, _dp, _vp, _d, _vp, _vp, _vp], _i),
+    "dg2p_rhs_vjp": ([_vp, ctypes.POINTER(Params), _dp, _dp, _dp, _dp, _vp, _vp], _i),
+    "dg2p_rk_step_vjp": ([_vp, ctypes.POINTER(Params), _dp, _dp, _dp, _dp, _dp, _vp, _vp], _i),
+    "dg2p_prim_to_cons_vjp": ([_vp, ctypes.POINTER(Params), _dp, _dp, _dp, _vp], _i),
+    "dg2p_node_weights": ([_vp, _dp], _i),
     "dg2p_timing_enable": ([_i], _i),
     "dg2p_timing_read": ([_i, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_longlong)], _i),
 }
-K_INGREDIENTS, K_STAGE, K_RATE, K_RATE_FINAL, K_MONITOR, K_PRIM = range(6)
+K_INGREDIENTS, K_STAGE, K_RATE, K_RATE_FINAL, K_MONITOR, K_PRIM, K_VJP_LOCAL, K_VJP_GATHER = range(8)
 for _name, (_args, _res) in _SIG.items():
     _fn = getattr(_lib, _name)
     _fn.argtypes = _args
@@ -172,6 +176,11 @@ class Mesh:
         _check(_lib.dg2p_node_coords(self._h, out.ctypes.data_as(ctypes.c_void_p)), "dg2p_node_coords")
         return out
 
+    def node_weights(self):
+        out = np.empty(self.nn, dtype=np.float64)
+        _check(_lib.dg2p_node_weights(self._h, out.ctypes.data_as(ctypes.c_void_p)), "dg2p_node_weights")
+        return out
+
     def workspace_bytes(self, params, op):
         n = ctypes.c_size_t()
         _check(_lib.dg2p_workspace_size(self._h, ctypes.byref(params), op, ctypes.byref(n)),
@@ -204,6 +213,15 @@ def prim_to_cons(mesh, params, prim, stream=None):
     _check(_lib.dg2p_prim_to_cons(mesh.handle, ctypes.byref(params), _ptr(prim), _ptr(U),
                                   _stream(stream)), "dg2p_prim_to_cons")
     return U
+
+
+def prim_to_cons_vjp(mesh, params, prim, U_bar, stream=None):
+    prim = _as_state(mesh, prim)
+    U_bar = _as_state(mesh, U_bar)
+    out = torch.empty_like(prim)
+    _check(_lib.dg2p_prim_to_cons_vjp(mesh.handle, ctypes.byref(params), _ptr(prim), _ptr(U_bar), _ptr(out),
+                                      _stream(stream)), "dg2p_prim_to_cons_vjp")
+    return out
 
 
 def rhs(mesh, params, U, out=None, stream=None):
@@ -247,6 +265,28 @@ def advance(mesh, params, U, n_steps, cfl=0.1, dt_fixed=None, t=None, dt_last=No
                              _ptr(dt_fixed), _ptr(t), _ptr(dt_last), _ptr(mon), float(p_ref),
                              ctypes.cast(ur, ctypes.c_void_p), ws, _stream(stream)), "dg2p_advance")
     return U
+
+
+def rhs_vjp(mesh, params, U, R_bar, param_bar=None, stream=None):
+    """U_bar = (dR/dU)^T R_bar; param_bar (1-element device tensor) += sigma cotangent."""
+    U = _as_state(mesh, U)
+    R_bar = _as_state(mesh, R_bar)
+    Ub = torch.empty_like(U)
+    ws = mesh.workspace(params, OP_RHS_VJP, U.device)
+    _check(_lib.dg2p_rhs_vjp(mesh.handle, ctypes.byref(params), _ptr(U), _ptr(R_bar), _ptr(Ub),
+                             _ptr(param_bar), ws, _stream(stream)), "dg2p_rhs_vjp")
+    return Ub
+
+
+def rk_step_vjp(mesh, params, U_n, dt, U_np1_bar, param_bar=None, out=None, stream=None):
+    """U_n_bar = (dU_{n+1}/dU_n)^T U_np1_bar for one SSP-RK3 step with device dt."""
+    U_n = _as_state(mesh, U_n)
+    U_np1_bar = _as_state(mesh, U_np1_bar)
+    Ub = torch.empty_like(U_n) if out is None else out
+    ws = mesh.workspace(params, OP_RK_STEP_VJP, U_n.device)
+    _check(_lib.dg2p_rk_step_vjp(mesh.handle, ctypes.byref(params), _ptr(U_n), _ptr(dt), _ptr(U_np1_bar),
+                                 _ptr(Ub), _ptr(param_bar), ws, _stream(stream)), "dg2p_rk_step_vjp")
+    return Ub
 
 
 def decode_monitors(buf, nf):

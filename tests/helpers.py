@@ -7,10 +7,15 @@ import oracle
 from paper_2306_05002_amd import workloads
 
 
-def oracle_setup(name, n_elem=None, variant=None, **param_over):
-    """(cfg, mesh, params, U0) for a configuration, built on the oracle side."""
+def oracle_setup(name, n_elem=None, variant=None, bc=None, **param_over):
+    """(cfg, mesh, params, U0) for a configuration, built on the oracle side.
+    ``bc`` overrides the boundary kinds (e.g. all periodic)."""
     cfg = workloads.config(name, n_elem=n_elem)
-    prm = oracle.Params(**{**cfg["params"], **param_over})
+    if bc is not None:
+        cfg["bc"] = bc
+        cfg["bc_prim"] = {}
+    cfg["params"] = {**cfg["params"], **param_over}   # overrides reach the initial state too
+    prm = oracle.Params(**cfg["params"])
     d = cfg["dim"]
     bc_state = {}
     for key, bp in cfg.get("bc_prim", {}).items():

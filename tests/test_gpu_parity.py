@@ -28,8 +28,8 @@ def _dg():
     return dg2p
 
 
-def gpu_case(name, n_elem=None, variant=None, **over):
-    cfg, om, prm, U0 = oracle_setup(name, n_elem=n_elem, variant=variant, **over)
+def gpu_case(name, n_elem=None, variant=None, bc=None, **over):
+    cfg, om, prm, U0 = oracle_setup(name, n_elem=n_elem, variant=variant, bc=bc, **over)
     dg = _dg()
     P = dg.make_params({**cfg["params"], **over})
     mesh = dg.mesh_from_config(dict(cfg, params={**cfg["params"], **over}), P)
@@ -270,6 +270,96 @@ def test_mixed_precision_interface_equilibrium():
     m = dg.monitors(mesh, Pm, U, p_ref=1.0, u_ref=[1.0, 0.5])
     print("fp32 IEC after 50 steps", m["dev_p"], m["dev_u"])
     assert m["dev_p"] < 1e-5 and m["dev_u"] < 1e-5 and m["nonphys"] == 0
+
+
+# ---- hand-written adjoint vs the oracle's autograd adjoint ---------------------------
+PERIODIC3 = [("periodic", "periodic")] * 3
+# (name, elements, boundary override, parameter overrides, tolerance).  The CSF
+# delta function |grad alpha| is differentiated through grad alpha / |grad alpha|;
+# where alpha is within ~1e-11 of 0 or 1, grad alpha comes out of a
+# cancellation (relative rounding ~1e-7 on each side), so with the thin
+# interface of the workloads the surface-tension part of the alpha cotangent
+# is conditioned at ~1e-9: those cases carry 1e-8.  The same physics with a
+# thick interface (eps = 0.05, no cancellation) must agree to round-off.
+VJP_CASES = [("drop1d", (13,), None, {}, 1e-11), ("drop2d", (6, 5), None, {}, 1e-11),
+             ("adjoint2d", (6, 5), None, {"eps": 0.05}, 1e-11),
+             ("adjoint2d", (5, 3), None, {"eps": 0.05}, 1e-11),
+             ("adjoint2d", (6, 5), None, {}, 1e-8),
+             ("rt3d", (3, 2, 4), PERIODIC3, {"eps": 0.05}, 1e-11),
+             ("rt3d", (3, 2, 4), PERIODIC3, {}, 1e-8)]
+
+
+def vjp_errors(Ug, Uo):
+    top = float(Uo.abs().max())
+    return [float((Ug[f] - Uo[f]).abs().max()) / max(float(Uo[f].abs().max()), 1e-3 * top)
+            for f in range(Uo.shape[0])]
+
+
+@pytest.mark.parametrize("name,ne,bc,over,tol", VJP_CASES)
+def test_rhs_vjp_parity(name, ne, bc, over, tol):
+    cfg, om, prm, U0, mesh, P = gpu_case(name, ne, bc=bc, **over)
+    dg = _dg()
+    w = torch.randn(U0.shape, generator=torch.Generator().manual_seed(11), dtype=torch.float64)
+    Ubo, sbo = oracle.adjoint.rhs_vjp(U0, w, om, prm)
+    pbar = torch.zeros(1, dtype=torch.float64, device="cuda")
+    Ubg = dg.rhs_vjp(mesh, P, U0.cuda().contiguous(), w.cuda().contiguous(), param_bar=pbar).cpu()
+    errs = vjp_errors(Ubg, Ubo)
+    print(name, ne, over, ["%.1e" % x for x in errs], float(pbar.cpu()), sbo)
+    assert max(errs) <= tol, errs
+    # R is affine in sigma: dR/dsigma = R(sigma=1) - R(sigma=0) exactly; the sigma
+    # cotangent is compared against the absolute size of its terms (in 1D the
+    # curvature of a +-1 normal is round-off, so sigma_bar itself is noise there)
+    import dataclasses
+    dR = oracle.rhs(U0, om, dataclasses.replace(prm, sigma=1.0)) - oracle.rhs(U0, om, dataclasses.replace(prm, sigma=0.0))
+    scale = float((w.abs() * dR.abs()).sum())
+    if om.d >= 2:
+        assert abs(float(pbar.cpu()) - sbo) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("name,ne,bc,over,tol", [("adjoint2d", (5, 4), None, {"eps": 0.05}, 1e-11),
+                                                 ("adjoint2d", (5, 4), None, {}, 1e-8),
+                                                 ("rt3d", (2, 2, 3), PERIODIC3, {"eps": 0.05}, 1e-11),
+                                                 ("drop1d", (11,), None, {}, 1e-11)])
+def test_rk_step_vjp_parity(name, ne, bc, over, tol):
+    cfg, om, prm, U0, mesh, P = gpu_case(name, ne, bc=bc, **over)
+    dg = _dg()
+    dt = oracle.max_dt(U0, om, prm)
+    w = torch.randn(U0.shape, generator=torch.Generator().manual_seed(12), dtype=torch.float64)
+    Ubo, sbo = oracle.adjoint.rk_step_vjp(U0, dt, w, om, prm)
+    pbar = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dtd = torch.tensor([dt], dtype=torch.float64, device="cuda")
+    Ubg = dg.rk_step_vjp(mesh, P, U0.cuda().contiguous(), dtd, w.cuda().contiguous(), param_bar=pbar).cpu()
+    errs = vjp_errors(Ubg, Ubo)
+    print(name, over, ["%.1e" % x for x in errs], float(pbar.cpu()), sbo)
+    assert max(errs) <= tol, errs
+    if om.d >= 2:   # in 1D the curvature is round-off (see the residual test)
+        assert abs(float(pbar.cpu()) - sbo) <= 1e-10 * abs(sbo)
+
+
+def test_rhs_vjp_dot_product_gpu():
+    """<J v, w> from central differences of the GPU residual equals <v, J^T w>
+    (resolved interface, so the residual is smooth at the difference step)."""
+    cfg, om, prm, U0, mesh, P = gpu_case("adjoint2d", (8, 8), eps=0.05)
+    dg = _dg()
+    g = torch.Generator().manual_seed(3)
+    scale = U0.abs().amax(dim=(1, 2), keepdim=True)
+    v = (torch.randn(U0.shape, generator=g, dtype=torch.float64) * scale * 1e-3).cuda()
+    w = torch.randn(U0.shape, generator=g, dtype=torch.float64).cuda()
+    U = U0.cuda().contiguous()
+    h = 1e-6
+    Jv = (dg.rhs(mesh, P, (U + h * v).contiguous()) - dg.rhs(mesh, P, (U - h * v).contiguous())) / (2 * h)
+    Ub = dg.rhs_vjp(mesh, P, U, w.contiguous())
+    lhs, rhs_ = float((Jv * w).sum()), float((v * Ub).sum())
+    assert abs(lhs - rhs_) <= 1e-6 * max(abs(lhs), abs(rhs_))
+
+
+def test_vjp_rejects_unsupported():
+    cfg, om, prm, U0, mesh, P = gpu_case("shock2d", (4, 3))
+    dg = _dg()
+    U = U0.cuda().contiguous()
+    with pytest.raises(dg.Dg2pError) as ei:
+        dg.rhs_vjp(mesh, P, U, U.clone())
+    assert ei.value.status == dg.EUNSUPPORTED
 
 
 FULL = ["drop2d", "shock2d", "adjoint2d", "rt3d"]
