@@ -135,7 +135,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip the mixed-precision timings")
+                    help="skip the mixed-precision and adjoint measurements")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -217,6 +217,46 @@ def main():
                               "contractions": prec, "closure_and_rk": "fp64"}
             del Um
 
+    # adjoint form: VJP of one SSP-RK3 step on the adjoint workload (viscous +
+    # CSF droplet, 128 x 128, frozen dt), and its central-difference agreement
+    adjoint = None
+    if not args.no_variants:
+        from paper_2306_05002_amd import adjoint as adj
+        prob = adj.AdjointProblem()
+        Ua = dg2p.prim_to_cons(prob.mesh, prob.P, prob.prim0)
+        Wb = torch.randn(Ua.shape, dtype=torch.float64, device="cuda",
+                         generator=torch.Generator(device="cuda").manual_seed(0))
+        Ub = torch.empty_like(Ua)
+        sb = torch.zeros(1, dtype=torch.float64, device="cuda")
+        for _ in range(3):
+            dg2p.rk_step_vjp(prob.mesh, prob.P, Ua, prob.dt, Wb, param_bar=sb, out=Ub)
+        torch.cuda.synchronize()
+        n_adj = max(5, min(args.steps, 50))
+        e0.record(stream)
+        for _ in range(n_adj):
+            dg2p.rk_step_vjp(prob.mesh, prob.P, Ua, prob.dt, Wb, param_bar=sb, out=Ub)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_vjp = e0.elapsed_time(e1) / n_adj
+        dof_a = prob.mesh.E * prob.mesh.nn * prob.mesh.nf
+        L0, gu, gs = prob.gradient()
+        worst = 0.0
+        h = 1e-6
+        for k in range(16):
+            du, ds = prob.fd_directions(k)
+            with torch.no_grad():
+                Lp = float(prob.loss(prob.u0 + h * du, prob.sigma0 + h * ds))
+                Lm = float(prob.loss(prob.u0 - h * du, prob.sigma0 - h * ds))
+            fd = (Lp - Lm) / (2 * h)
+            ad = float((gu * du).sum()) + gs * ds
+            worst = max(worst, abs(fd - ad) / max(abs(fd), abs(ad), 1e-300))
+        adjoint = {"workload": "adjoint2d: droplet 128x128 p=3, viscous + CSF, 400 steps, checkpoint every 20",
+                   "value": 3.0 * dof_a / (ms_vjp * 1e-3), "unit": "DOF-updates/s",
+                   "ms_per_step_vjp": ms_vjp,
+                   "step_vjp": "recompute 2 stages + 3 residual VJPs (local + gather)",
+                   "fd_directions": 16, "fd_step": h, "fd_max_rel_err": worst,
+                   "dL_dsigma": gs}
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg, args.cpu_seconds)
@@ -257,6 +297,7 @@ def main():
         },
         "kernels_mean_ms": {k: v[0] for k, v in k_ms.items()},
         "mixed_precision": variants,
+        "adjoint": adjoint,
         "cpu_baseline": cpu,
         "monitors": {"nonphys": mon["nonphys"], "min_alpha": mon["min_alpha"],
                      "max_alpha": mon["max_alpha"]},
