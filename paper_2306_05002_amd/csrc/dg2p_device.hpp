@@ -38,6 +38,25 @@
 namespace dg2p {
 
 constexpr int BLOCK = 256;      // threads per workgroup (4 independent waves)
+// minimum resident waves per SIMD the register allocator targets, per dimension
+#ifndef DG2P_WAVES_1D
+#define DG2P_WAVES_1D 4
+#endif
+#ifndef DG2P_WAVES_2D
+#define DG2P_WAVES_2D 3
+#endif
+#ifndef DG2P_WAVES_3D
+#define DG2P_WAVES_3D 1
+#endif
+// issue the face-neighbour loads at kernel entry (hides their latency behind
+// the volume terms at the cost of registers); used where waves are few
+#ifndef DG2P_PREFETCH_MAXDIM
+#define DG2P_PREFETCH_MAXDIM 0
+#endif
+template <int DIM>
+constexpr int min_waves() {
+  return DIM == 1 ? DG2P_WAVES_1D : (DIM == 2 ? DG2P_WAVES_2D : DG2P_WAVES_3D);
+}
 constexpr int REC = 16;         // doubles per reduction record
 // record slots
 constexpr int R_WAVE = 0, R_NU = 1, R_AMIN = 2, R_AMAX = 3, R_BAD = 4, R_DEVP = 5, R_DEVU = 6,
@@ -138,8 +157,8 @@ __device__ __forceinline__ double sel4(int a, double c0, double c1, double c2, d
 template <int CTRL>
 __device__ __forceinline__ double dpp64(double v) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), CTRL, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(b & 0xffffffffull), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 // quad rotation: lane a of a quad receives lane (a + R) & 3
@@ -214,7 +233,7 @@ __device__ __forceinline__ double dk(double f, int k, const LaneD<DIM>& L, const
 // lane exchanges and accumulated in FP32.
 template <int CTRL>
 __device__ __forceinline__ float dpp32(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 __device__ __forceinline__ float bf16_round(float x) {
   unsigned u = __float_as_uint(x);
@@ -624,7 +643,7 @@ __global__ __launch_bounds__(BLOCK) void k_ingredients(KArgs A, const double* __
 // MODE 2: U_out = rk_a U_n + rk_b (U_s + dt R).  Epilogue on U_out: EPI = 1
 // face ingredients into Gout, EPI = 2 also the reduction records.
 template <int DIM, bool VISC, bool CSF, bool DIRI, int MODE, int EPI, int PR>
-__global__ __launch_bounds__(BLOCK) void k_stage(KArgs A, StageIO io) {
+__global__ __launch_bounds__(BLOCK, min_waves<DIM>()) void k_stage(KArgs A, StageIO io) {
   constexpr int NN = 1 << (2 * DIM);
   constexpr int EPW = 64 / NN;
   constexpr int NF = DIM + 5;
@@ -648,6 +667,55 @@ __global__ __launch_bounds__(BLOCK) void k_stage(KArgs A, StageIO io) {
   double q[NF];
 #pragma unroll
   for (int f = 0; f < NF; ++f) q[f] = Us[(f * A.E + e) * NN + node];
+  // element multi-index and face neighbours
+  long long ec[3] = {0, 0, 0};
+  {
+    long long r = e;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      ec[k] = r % A.N[k];
+      r /= A.N[k];
+    }
+  }
+  constexpr bool PF = DIM <= DG2P_PREFETCH_MAXDIM;
+  long long enb[DIM];
+  bool bndk[DIM];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    const int akk = ak[k];
+    const bool isface = (akk == 0) || (akk == 3);
+    const int side = akk == 3;
+    long long c = ec[k] + (side ? 1 : -1);
+    bool bnd = false;
+    if (c < 0 || c >= A.N[k]) {
+      if (A.bc[k][side] == DG2P_BC_PERIODIC)
+        c = (c < 0) ? A.N[k] - 1 : 0;
+      else
+        bnd = true;
+    }
+    long long estr = 1;
+#pragma unroll
+    for (int kk = 0; kk < k; ++kk) estr *= A.N[kk];
+    enb[k] = (isface && !bnd) ? e + (c - ec[k]) * estr : e;
+    bndk[k] = bnd;
+  }
+  double qpf[PF ? DIM : 1][NF];
+  double apf[PF ? DIM : 1][C];
+  if constexpr (PF) {
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      const int akk = ak[k];
+      const bool isface = (akk == 0) || (akk == 3);
+      const int nodee = isface ? node + (3 - 2 * akk) * (1 << (2 * k)) : node;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) qpf[k][f] = Us[(f * A.E + enb[k]) * NN + nodee];
+      const int side = akk == 3;
+      const int fn = face_index(node, k);
+      const long long gb = (long long)((2 * k + 1 - side) * C) * A.E;
+#pragma unroll
+      for (int cc = 0; cc < C; ++cc) apf[k][cc] = io.Gin[(gb + (long long)cc * A.E + enb[k]) * NFN + fn];
+    }
+  }
   Prim pr;
   closure<DIM>(A, q, pr);
   Grad<DIM, VISC> g;
@@ -718,15 +786,6 @@ __global__ __launch_bounds__(BLOCK) void k_stage(KArgs A, StageIO io) {
   }
 
   // faces
-  long long ec[3] = {0, 0, 0};
-  {
-    long long r = e;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      ec[k] = r % A.N[k];
-      r /= A.N[k];
-    }
-  }
   const double* __restrict__ Gin = io.Gin;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
@@ -739,31 +798,31 @@ __global__ __launch_bounds__(BLOCK) void k_stage(KArgs A, StageIO io) {
     if (isface) {
       const int side = akk == 3;
       const double sm = side ? 1.0 : -1.0;
-      long long c = ec[k] + (side ? 1 : -1);
-      bool bnd = false;
-      if (c < 0 || c >= A.N[k]) {
-        if (A.bc[k][side] == DG2P_BC_PERIODIC)
-          c = (c < 0) ? A.N[k] - 1 : 0;
-        else
-          bnd = true;
-      }
+      const bool bnd = bndk[k];
       double qe[NF];
       double aek;
       double tek[DIM];
       if (!bnd) {
-        long long estr = 1;
+        if constexpr (PF) {
 #pragma unroll
-        for (int kk = 0; kk < k; ++kk) estr *= A.N[kk];
-        const long long en = e + (c - ec[k]) * estr;
-        const int nodee = node + (3 - 2 * akk) * S;
+          for (int f = 0; f < NF; ++f) qe[f] = qpf[k][f];
+          aek = apf[k][0];
+          if constexpr (VISC) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) qe[f] = Us[(f * A.E + en) * NN + nodee];
-        const int fn = face_index(node, k);
-        const long long gb = (long long)((2 * k + 1 - side) * C) * A.E;
-        aek = Gin[(gb + en) * NFN + fn];
-        if constexpr (VISC) {
+            for (int j = 0; j < DIM; ++j) tek[j] = apf[k][(1 + j) < C ? 1 + j : 0];
+          }
+        } else {
+          const long long en = enb[k];
+          const int nodee = node + (3 - 2 * akk) * S;
 #pragma unroll
-          for (int j = 0; j < DIM; ++j) tek[j] = Gin[(gb + (long long)(1 + j) * A.E + en) * NFN + fn];
+          for (int f = 0; f < NF; ++f) qe[f] = Us[(f * A.E + en) * NN + nodee];
+          const int fn = face_index(node, k);
+          const long long gb = (long long)((2 * k + 1 - side) * C) * A.E;
+          aek = Gin[(gb + en) * NFN + fn];
+          if constexpr (VISC) {
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) tek[j] = Gin[(gb + (long long)(1 + j) * A.E + en) * NFN + fn];
+          }
         }
       } else {
         const int kind = A.bc[k][side];
