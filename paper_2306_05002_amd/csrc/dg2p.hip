@@ -281,6 +281,8 @@ void launch_stage_p(int mode, int epi, const KArgs& A, const StageIO& io, hipStr
     hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 2, 1, PR>), g, b, 0, s, A, io);
   else if (epi == 2)
     hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 2, 2, PR>), g, b, 0, s, A, io);
+  else if (epi == 3)
+    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 2, 3, PR>), g, b, 0, s, A, io);
   else
     hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 2, 0, PR>), g, b, 0, s, A, io);
 }
@@ -364,7 +366,7 @@ void finalize(const dg2p_mesh_s* m, const KArgs& A, const Work& w, long long n, 
               double* dt, double* t, dg2p_monitors* mon, hipStream_t s) {
   TimedLaunch tl(DG2P_K_RATE_FINAL, s);
   const double* src = w.rec;
-  if (n > 4 * BLOCK) {
+  if (n > FIN_THREADS) {
     long long chunk = (n + REC2_MAX - 1) / REC2_MAX;
     if (chunk < BLOCK) chunk = BLOCK;
     const long long nb = (n + chunk - 1) / chunk;
@@ -374,7 +376,7 @@ void finalize(const dg2p_mesh_s* m, const KArgs& A, const Work& w, long long n, 
   }
   double hmin = m->h[0];
   for (int k = 1; k < m->dim; ++k) hmin = std::fmin(hmin, m->h[k]);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLOCK), 0, s, src, n, A.GammaEps, m->dim, m->nf, hmin, cfl,
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, s, src, n, A.GammaEps, m->dim, m->nf, hmin, cfl,
                      dt_fixed, dt, t, mon);
 }
 
@@ -666,12 +668,16 @@ int dg2p_advance(dg2p_mesh m, const dg2p_params* p, double* U, int n_steps, doub
     B.rk_a = 1.0 / 3.0;
     B.rk_b = 2.0 / 3.0;
     StageIO io3{w.U2, Ga, U, U, Gb, w.rec, dts};
-    launch_stage(m, p, 2, 2, B, io3, s);
+    launch_stage(m, p, 2, 3, B, io3, s);
     double* tmp = Ga;
     Ga = Gb;
     Gb = tmp;
   }
-  if (mon) finalize(m, A, w, nrec, cfl, nullptr, nullptr, nullptr, mon, s);
+  if (mon) {
+    // monitors of the final state (the per-step records carry the rate only)
+    launch_records(m, p, A, U, w.rec, s);
+    finalize(m, A, w, records_of_records(m, p, 1), cfl, nullptr, nullptr, nullptr, mon, s);
+  }
   return hip_check(hipGetLastError(), "advance launch");
 }
 

@@ -447,6 +447,31 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Rate-only record: wave max of two values, then the workgroup's 4 waves;
+// the other slots get the identities of their reductions.
+__device__ __forceinline__ void block_rate_record(double w, double nu, double* rec, long long blk) {
+  __shared__ double sh[2][BLOCK / 64];
+  w = wave_max(w);
+  nu = wave_max(nu);
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = w;
+    sh[1][threadIdx.x >> 6] = nu;
+  }
+  __syncthreads();
+  if (threadIdx.x < REC) {
+    const int s = threadIdx.x;
+    double x;
+    if (s == R_WAVE || s == R_NU) {
+      x = sh[s][0];
+#pragma unroll
+      for (int i = 1; i < BLOCK / 64; ++i) x = fmax(x, sh[s][i]);
+    } else {
+      x = (s == R_AMIN) ? INFINITY : (s == R_AMAX ? -INFINITY : 0.0);
+    }
+    rec[blk * REC + s] = x;
+  }
+}
+
 // Per-node record contributions of a state (time-step rate and monitors).
 template <int DIM, bool VISC>
 __device__ __forceinline__ void node_record(const KArgs& A, const double* q, const Prim& p, int node,
@@ -577,7 +602,7 @@ __device__ __forceinline__ long long logical_block(const KArgs& A) {
 }
 
 // ---- epilogue: face ingredients and records of a state held per lane ----------------
-template <int DIM, bool VISC, bool WRITE_G, bool WRITE_REC, int PR>
+template <int DIM, bool VISC, bool WRITE_G, int REC_MODE, int PR>
 __device__ __forceinline__ void emit(const KArgs& A, const double* q, long long e, bool valid, int node,
                                      const int* ak, const Deriv<DIM, PR>& L, double* G, double* rec,
                                      long long blk) {
@@ -604,10 +629,21 @@ __device__ __forceinline__ void emit(const KArgs& A, const double* q, long long 
       }
     }
   }
-  if constexpr (WRITE_REC) {
+  if constexpr (REC_MODE == 2) {
     double v[REC];
     node_record<DIM, VISC>(A, q, p, node, valid, v);
     block_record(v, rec, blk);
+  } else if constexpr (REC_MODE == 1) {
+    // time-step rate only: largest wave speed and kinematic viscosity
+    double w = DIM * p.c;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) w += fabs(p.u[j]);
+    double nu = 0.0;
+    if constexpr (VISC) {
+      const double al = q[3 + DIM];
+      nu = (A.mu1 * al + A.mu2 * (1.0 - al)) / p.rho;
+    }
+    block_rate_record(valid ? w : 0.0, valid ? nu : 0.0, rec, blk);
   }
 }
 
@@ -634,7 +670,7 @@ __global__ __launch_bounds__(BLOCK) void k_ingredients(KArgs A, const double* __
   double q[NF];
 #pragma unroll
   for (int f = 0; f < NF; ++f) q[f] = U[(f * A.E + e) * NN + node];
-  emit<DIM, VISC, true, true, PR>(A, q, e, valid, node, ak, L, G, rec, blk);
+  emit<DIM, VISC, true, 2, PR>(A, q, e, valid, node, ak, L, G, rec, blk);
 }
 
 // ---------------------------------------------------------------------------
@@ -955,7 +991,8 @@ __global__ __launch_bounds__(BLOCK, min_waves<DIM>()) void k_stage(KArgs A, Stag
 #pragma unroll
       for (int f = 0; f < NF; ++f) io.Out[f * fs + o] = uo[f];
     }
-    if constexpr (EPI > 0) emit<DIM, VISC, true, (EPI > 1), PR>(A, uo, e, valid, node, ak, L, io.Gout, io.rec, blk);
+    if constexpr (EPI > 0)
+      emit<DIM, VISC, true, (EPI == 2 ? 2 : (EPI == 3 ? 1 : 0)), PR>(A, uo, e, valid, node, ak, L, io.Gout, io.rec, blk);
   }
 }
 
@@ -1051,50 +1088,56 @@ __global__ __launch_bounds__(BLOCK) void k_records(KArgs A, const double* __rest
   block_record(acc, rec, blockIdx.x);
 }
 
+// Records are reduced with one slot per thread: thread t of a workgroup of NT
+// threads reads slot t mod REC of records lo + t / REC, lo + t / REC + NT / REC,
+// ... (contiguous loads), then threads holding the same slot are combined
+// (lanes 16 and 32 apart in the wave, then the waves through LDS).  The
+// combination order is fixed, so the result is deterministic.
+__device__ __forceinline__ double rec_identity(int slot) {
+  return slot == R_AMIN ? INFINITY : (slot == R_AMAX ? -INFINITY : 0.0);
+}
+template <int NT>
+__device__ __forceinline__ void reduce_slots(const double* __restrict__ rec, long long lo, long long hi,
+                                             double* red) {
+  static_assert(NT % 64 == 0 && 64 % REC == 0, "slot-per-thread layout");
+  const int s = threadIdx.x % REC;
+  double acc = rec_identity(s);
+  for (long long r = lo + threadIdx.x / REC; r < hi; r += NT / REC) acc = rec_combine(s, acc, rec[r * REC + s]);
+#pragma unroll
+  for (int m = REC; m < 64; m <<= 1) acc = rec_combine(s, acc, __shfl_xor(acc, m));
+  __shared__ double sh[NT / 64][REC];
+  if ((threadIdx.x & 63) < REC) sh[threadIdx.x >> 6][s] = acc;
+  __syncthreads();
+  if (threadIdx.x < REC) {
+    double x = sh[0][s];
+#pragma unroll
+    for (int i = 1; i < NT / 64; ++i) x = rec_combine(s, x, sh[i][s]);
+    red[s] = x;
+  }
+}
+
 // First-level reduction of records: workgroup j combines records
-// [j*chunk, min((j+1)*chunk, n)) in index order.
+// [j*chunk, min((j+1)*chunk, n)) into record j of out.
 __global__ __launch_bounds__(BLOCK) void k_reduce_records(const double* __restrict__ rec, long long n,
                                                           long long chunk, double* __restrict__ out) {
   const long long lo = (long long)blockIdx.x * chunk;
   const long long hi = lo + chunk < n ? lo + chunk : n;
-  double acc[REC];
-#pragma unroll
-  for (int s = 0; s < REC; ++s) acc[s] = (s == R_AMIN) ? INFINITY : (s == R_AMAX ? -INFINITY : 0.0);
-  for (long long r = lo + threadIdx.x; r < hi; r += BLOCK) {
-#pragma unroll
-    for (int s = 0; s < REC; ++s) acc[s] = rec_combine(s, acc[s], rec[r * REC + s]);
-  }
-  block_record(acc, out, blockIdx.x);
+  __shared__ double red[REC];
+  reduce_slots<BLOCK>(rec, lo, hi, red);
+  __syncthreads();
+  if (threadIdx.x < REC) out[(long long)blockIdx.x * REC + threadIdx.x] = red[threadIdx.x];
 }
 
 // Final reduction: time-step rule and monitors.  rate = (max wave + (p+1)^2 d
 // nu_max / h_min) / h_min with nu_max = max(Gamma eps, max mu/rho); dt = cfl / rate.
-__global__ __launch_bounds__(BLOCK) void k_finalize(const double* __restrict__ rec, long long n,
-                                                    double GammaEps, int dim, int nf, double hmin,
-                                                    double cfl, const double* dt_fixed, double* dt,
-                                                    double* t, dg2p_monitors* mon) {
-  double acc[REC];
-#pragma unroll
-  for (int s = 0; s < REC; ++s) acc[s] = (s == R_AMIN) ? INFINITY : (s == R_AMAX ? -INFINITY : 0.0);
-  for (long long r = threadIdx.x; r < n; r += BLOCK) {
-#pragma unroll
-    for (int s = 0; s < REC; ++s) acc[s] = rec_combine(s, acc[s], rec[r * REC + s]);
-  }
+// One workgroup of FIN_THREADS threads.
+constexpr int FIN_THREADS = 1024;
+__global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double* __restrict__ rec, long long n,
+                                                          double GammaEps, int dim, int nf, double hmin,
+                                                          double cfl, const double* dt_fixed, double* dt,
+                                                          double* t, dg2p_monitors* mon) {
   __shared__ double red[REC];
-  __shared__ double sh[REC][BLOCK / 64];
-  const int w = threadIdx.x >> 6;
-#pragma unroll
-  for (int s = 0; s < REC; ++s) {
-    const double x = rec_wave(s, acc[s]);
-    if ((threadIdx.x & 63) == 0) sh[s][w] = x;
-  }
-  __syncthreads();
-  if (threadIdx.x < REC) {
-    const int s = threadIdx.x;
-    double x = sh[s][0];
-    for (int i = 1; i < BLOCK / 64; ++i) x = rec_combine(s, x, sh[s][i]);
-    red[s] = x;
-  }
+  reduce_slots<FIN_THREADS>(rec, 0, n, red);
   __syncthreads();
   if (threadIdx.x == 0) {
     const double nu = fmax(GammaEps, red[R_NU]);

@@ -89,7 +89,7 @@ def config(name, n_elem=None):
     elif name == "shock2d":
         cfg.update(dim=2, lo=(0.0, 0.0), hi=(2.0, 1.0),
                    bc=[("dirichlet", "extrapolate"), ("periodic", "periodic")],
-                   steps=200)
+                   steps=200, shock_x=0.34, shock_width=3.0)
         rho_post, u_post, p_post = shock_states()
         cfg["bc_prim"] = {(0, 0): dict(alpha=1.0, psi=0.0, rho1=rho_post,
                                        rho2=base["rho0"][1], u=(u_post, 0.0),
@@ -169,7 +169,7 @@ def primitive_fields(cfg, coords, variant=None):
     elif name == "shock2d":
         psi = np.sqrt((X[0] - 0.5) ** 2 + (X[1] - 0.5) ** 2) - 0.1
         h = (cfg["hi"][0] - cfg["lo"][0]) / cfg["n_elem"][0]
-        w = _sigmoid(-(X[0] - 0.38) / (0.5 * h))
+        w = _sigmoid(-(X[0] - cfg["shock_x"]) / (cfg["shock_width"] * h))
         rho_post, u_post, p_post = shock_states()
         rho1 = w * rho_post + (1.0 - w) * 1.0
         u[0] = w * u_post
