@@ -361,6 +361,12 @@ long long records_of_records(const dg2p_mesh_s* m, const dg2p_params* p, int sta
   return elem_blocks(m);
 }
 
+double min_h(const dg2p_mesh_s* m) {
+  double hmin = m->h[0];
+  for (int k = 1; k < m->dim; ++k) hmin = std::fmin(hmin, m->h[k]);
+  return hmin;
+}
+
 // Reduce n records to dt / monitors (two levels when n is large).
 void finalize(const dg2p_mesh_s* m, const KArgs& A, const Work& w, long long n, double cfl, const double* dt_fixed,
               double* dt, double* t, dg2p_monitors* mon, hipStream_t s) {
@@ -370,15 +376,37 @@ void finalize(const dg2p_mesh_s* m, const KArgs& A, const Work& w, long long n, 
     long long chunk = (n + REC2_MAX - 1) / REC2_MAX;
     if (chunk < BLOCK) chunk = BLOCK;
     const long long nb = (n + chunk - 1) / chunk;
-    hipLaunchKernelGGL(k_reduce_records, dim3((unsigned)nb), dim3(BLOCK), 0, s, w.rec, n, chunk, w.rec2);
+    hipLaunchKernelGGL(k_reduce_records<REC>, dim3((unsigned)nb), dim3(BLOCK), 0, s, w.rec, n, chunk, w.rec2);
     src = w.rec2;
     n = nb;
   }
-  double hmin = m->h[0];
-  for (int k = 1; k < m->dim; ++k) hmin = std::fmin(hmin, m->h[k]);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, s, src, n, A.GammaEps, m->dim, m->nf, hmin, cfl,
-                     dt_fixed, dt, t, mon);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, s, src, n, A.GammaEps, m->dim, m->nf, min_h(m),
+                     cfl, dt_fixed, dt, t, mon);
 }
+
+// Reduce n rate records (2 doubles each) to *dt (two levels when n is large).
+void finalize_rate(const dg2p_mesh_s* m, const KArgs& A, const Work& w, long long n, double cfl,
+                   const double* dt_fixed, double* dt, double* t, hipStream_t s) {
+  TimedLaunch tl(DG2P_K_RATE_FINAL, s);
+  const double* src = w.rec;
+  if (n > FIN_THREADS) {
+    long long chunk = (n + REC2_MAX - 1) / REC2_MAX;
+    if (chunk < BLOCK) chunk = BLOCK;
+    const long long nb = (n + chunk - 1) / chunk;
+    hipLaunchKernelGGL(k_reduce_records<RATE>, dim3((unsigned)nb), dim3(BLOCK), 0, s, w.rec, n, chunk, w.rec2);
+    src = w.rec2;
+    n = nb;
+  }
+  hipLaunchKernelGGL(k_finalize_rate, dim3(1), dim3(FIN_THREADS), 0, s, src, n, A.GammaEps, m->dim, min_h(m), cfl,
+                     dt_fixed, dt, t);
+}
+
+// Largest number of rate records for which every workgroup of the first stage
+// reduces them itself (16 KB per workgroup) instead of a separate reduction.
+#ifndef DG2P_FUSED_DT_MAX
+#define DG2P_FUSED_DT_MAX 1024
+#endif
+constexpr long long FUSED_DT_MAX = DG2P_FUSED_DT_MAX;
 
 bool all_periodic(const dg2p_mesh_s* m) {
   for (int k = 0; k < m->dim; ++k)
@@ -654,12 +682,25 @@ int dg2p_advance(dg2p_mesh m, const dg2p_params* p, double* U, int n_steps, doub
   double* dts = dt_last ? dt_last : w.dt;
   double* Ga = w.G0;
   double* Gb = w.G1;
-  const long long nrec = records_of_records(m, p, 0);
+  // rate records (2 doubles per workgroup) of the ingredient pass and of
+  // every step's last stage; the next step's dt is reduced from them either
+  // inside its first stage (small grids) or by two small kernels
+  const long long nrate = elem_blocks(m);
+  const bool fused = nrate <= FUSED_DT_MAX;
+  A.cfl = cfl;
+  A.hmin = min_h(m);
+  A.nrate = nrate;
   launch_ingr(m, p, A, U, Ga, w.rec, s);
   for (int it = 0; it < n_steps; ++it) {
-    finalize(m, A, w, nrec, cfl, dt_fixed, dts, t, nullptr, s);
+    if (!fused) finalize_rate(m, A, w, nrate, cfl, dt_fixed, dts, t, s);
     KArgs B = A;
     StageIO io1{U, Ga, nullptr, w.U1, Gb, nullptr, dts};
+    if (fused) {
+      io1.rate_in = w.rec;
+      io1.dt_out = dts;
+      io1.t = t;
+      io1.dt_fixed = dt_fixed;
+    }
     launch_stage(m, p, 1, 1, B, io1, s);
     B.rk_a = 0.75;
     B.rk_b = 0.25;

@@ -133,6 +133,9 @@ struct KArgs {
   double rk_a, rk_b;
   // reference values of the monitor deviations
   double p_ref, u_ref[3];
+  // time-step rule of a fused step (dt reduced inside the first stage)
+  double cfl, hmin;
+  long long nrate;  // number of rate records
 };
 
 struct StageIO {
@@ -143,6 +146,13 @@ struct StageIO {
   double* Gout;       // face ingredients of Out (epilogue)
   double* rec;        // reduction records (epilogue)
   const double* dt;   // device time step
+  // fused time step (first stage only; dt_out == NULL: dt is read from *dt):
+  // every workgroup reduces the rate records rate_in (or takes *dt_fixed),
+  // workgroup 0 stores dt to *dt_out and adds it to *t
+  const double* rate_in;
+  double* dt_out;
+  double* t;
+  const double* dt_fixed;
 };
 
 struct Prim {
@@ -447,8 +457,9 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Rate-only record: wave max of two values, then the workgroup's 4 waves;
-// the other slots get the identities of their reductions.
+// Rate record of a workgroup (2 doubles: largest wave speed and largest
+// kinematic viscosity): wave max, then the workgroup's 4 waves.
+constexpr int RATE = 2;
 __device__ __forceinline__ void block_rate_record(double w, double nu, double* rec, long long blk) {
   __shared__ double sh[2][BLOCK / 64];
   w = wave_max(w);
@@ -458,18 +469,60 @@ __device__ __forceinline__ void block_rate_record(double w, double nu, double* r
     sh[1][threadIdx.x >> 6] = nu;
   }
   __syncthreads();
-  if (threadIdx.x < REC) {
-    const int s = threadIdx.x;
-    double x;
-    if (s == R_WAVE || s == R_NU) {
-      x = sh[s][0];
+  if (threadIdx.x < RATE) {
+    const int s = threadIdx.x;  // R_WAVE, R_NU
+    double x = sh[s][0];
 #pragma unroll
-      for (int i = 1; i < BLOCK / 64; ++i) x = fmax(x, sh[s][i]);
-    } else {
-      x = (s == R_AMIN) ? INFINITY : (s == R_AMAX ? -INFINITY : 0.0);
-    }
-    rec[blk * REC + s] = x;
+    for (int i = 1; i < BLOCK / 64; ++i) x = fmax(x, sh[s][i]);
+    rec[blk * RATE + s] = x;
   }
+}
+
+// Time-step rule from the reduced maxima: rate = (max wave + (p+1)^2 d
+// nu_max / h_min) / h_min with nu_max = max(Gamma eps, max mu/rho).
+__device__ __forceinline__ double rate_of(double wmax, double numax, double GammaEps, int dim, double hmin) {
+  const double nu = fmax(GammaEps, numax);
+  return (wmax + 16.0 * dim * nu / hmin) / hmin;
+}
+
+// Fused time step of a small grid: every workgroup reduces all rate records
+// (batches of independent loads; max is exact, so every workgroup obtains
+// the same value as the separate reduction kernels).
+__device__ __forceinline__ double fused_dt(const KArgs& A, const double* __restrict__ rate, const double* dt_fixed,
+                                           int dim) {
+  if (dt_fixed) return *dt_fixed;
+  constexpr int RB = 4;
+  double w = 0.0, nu = 0.0;
+  for (long long r0 = threadIdx.x; r0 < A.nrate; r0 += RB * BLOCK) {
+    double vw[RB], vn[RB];
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+      const long long r = r0 + u * BLOCK;
+      vw[u] = r < A.nrate ? rate[r * RATE + R_WAVE] : 0.0;
+      vn[u] = r < A.nrate ? rate[r * RATE + R_NU] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+      w = fmax(w, vw[u]);
+      nu = fmax(nu, vn[u]);
+    }
+  }
+  w = wave_max(w);
+  nu = wave_max(nu);
+  __shared__ double sh[2][BLOCK / 64];
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = w;
+    sh[1][threadIdx.x >> 6] = nu;
+  }
+  __syncthreads();
+  w = sh[0][0];
+  nu = sh[1][0];
+#pragma unroll
+  for (int i = 1; i < BLOCK / 64; ++i) {
+    w = fmax(w, sh[0][i]);
+    nu = fmax(nu, sh[1][i]);
+  }
+  return A.cfl / rate_of(w, nu, A.GammaEps, dim, A.hmin);
 }
 
 // Per-node record contributions of a state (time-step rate and monitors).
@@ -670,7 +723,7 @@ __global__ __launch_bounds__(BLOCK) void k_ingredients(KArgs A, const double* __
   double q[NF];
 #pragma unroll
   for (int f = 0; f < NF; ++f) q[f] = U[(f * A.E + e) * NN + node];
-  emit<DIM, VISC, true, 2, PR>(A, q, e, valid, node, ak, L, G, rec, blk);
+  emit<DIM, VISC, true, 1, PR>(A, q, e, valid, node, ak, L, G, rec, blk);
 }
 
 // ---------------------------------------------------------------------------
@@ -750,6 +803,16 @@ __global__ __launch_bounds__(BLOCK, min_waves<DIM>()) void k_stage(KArgs A, Stag
       const long long gb = (long long)((2 * k + 1 - side) * C) * A.E;
 #pragma unroll
       for (int cc = 0; cc < C; ++cc) apf[k][cc] = io.Gin[(gb + (long long)cc * A.E + enb[k]) * NFN + fn];
+    }
+  }
+  double dt_fused = 0.0;
+  if constexpr (MODE == 1) {
+    if (io.dt_out) {  // uniform: the fused time step of a small grid
+      dt_fused = fused_dt(A, io.rate_in, io.dt_fixed, DIM);
+      if (blk == 0 && threadIdx.x == 0) {
+        *io.dt_out = dt_fused;
+        if (io.t) *io.t += dt_fused;
+      }
     }
   }
   Prim pr;
@@ -978,7 +1041,7 @@ __global__ __launch_bounds__(BLOCK, min_waves<DIM>()) void k_stage(KArgs A, Stag
       for (int f = 0; f < NF; ++f) io.Out[f * fs + o] = R[f];
     }
   } else {
-    const double dt = *io.dt;
+    const double dt = (MODE == 1 && io.dt_out) ? dt_fused : *io.dt;
     double uo[NF];
     if constexpr (MODE == 1) {
 #pragma unroll
@@ -1096,19 +1159,33 @@ __global__ __launch_bounds__(BLOCK) void k_records(KArgs A, const double* __rest
 __device__ __forceinline__ double rec_identity(int slot) {
   return slot == R_AMIN ? INFINITY : (slot == R_AMAX ? -INFINITY : 0.0);
 }
-template <int NT>
+template <int NS, int NT>
 __device__ __forceinline__ void reduce_slots(const double* __restrict__ rec, long long lo, long long hi,
                                              double* red) {
-  static_assert(NT % 64 == 0 && 64 % REC == 0, "slot-per-thread layout");
-  const int s = threadIdx.x % REC;
-  double acc = rec_identity(s);
-  for (long long r = lo + threadIdx.x / REC; r < hi; r += NT / REC) acc = rec_combine(s, acc, rec[r * REC + s]);
+  static_assert(NT % 64 == 0 && 64 % NS == 0, "slot-per-thread layout");
+  const int s = threadIdx.x % NS;
+  const double id = rec_identity(s);
+  double acc = id;
+  // batches of RB independent loads in flight (the records come from other
+  // XCDs' caches, so each load is a long-latency trip), combined in order
+  constexpr int RB = 8;
+  constexpr long long ST = NT / NS;
+  for (long long r0 = lo + threadIdx.x / NS; r0 < hi; r0 += RB * ST) {
+    double v[RB];
 #pragma unroll
-  for (int m = REC; m < 64; m <<= 1) acc = rec_combine(s, acc, __shfl_xor(acc, m));
-  __shared__ double sh[NT / 64][REC];
-  if ((threadIdx.x & 63) < REC) sh[threadIdx.x >> 6][s] = acc;
+    for (int u = 0; u < RB; ++u) {
+      const long long r = r0 + u * ST;
+      v[u] = r < hi ? rec[r * NS + s] : id;
+    }
+#pragma unroll
+    for (int u = 0; u < RB; ++u) acc = rec_combine(s, acc, v[u]);
+  }
+#pragma unroll
+  for (int m = NS; m < 64; m <<= 1) acc = rec_combine(s, acc, __shfl_xor(acc, m));
+  __shared__ double sh[NT / 64][NS];
+  if ((threadIdx.x & 63) < NS) sh[threadIdx.x >> 6][s] = acc;
   __syncthreads();
-  if (threadIdx.x < REC) {
+  if (threadIdx.x < NS) {
     double x = sh[0][s];
 #pragma unroll
     for (int i = 1; i < NT / 64; ++i) x = rec_combine(s, x, sh[i][s]);
@@ -1116,16 +1193,17 @@ __device__ __forceinline__ void reduce_slots(const double* __restrict__ rec, lon
   }
 }
 
-// First-level reduction of records: workgroup j combines records
+// First-level reduction of records of NS slots: workgroup j combines records
 // [j*chunk, min((j+1)*chunk, n)) into record j of out.
+template <int NS>
 __global__ __launch_bounds__(BLOCK) void k_reduce_records(const double* __restrict__ rec, long long n,
                                                           long long chunk, double* __restrict__ out) {
   const long long lo = (long long)blockIdx.x * chunk;
   const long long hi = lo + chunk < n ? lo + chunk : n;
-  __shared__ double red[REC];
-  reduce_slots<BLOCK>(rec, lo, hi, red);
+  __shared__ double red[NS];
+  reduce_slots<NS, BLOCK>(rec, lo, hi, red);
   __syncthreads();
-  if (threadIdx.x < REC) out[(long long)blockIdx.x * REC + threadIdx.x] = red[threadIdx.x];
+  if (threadIdx.x < NS) out[(long long)blockIdx.x * NS + threadIdx.x] = red[threadIdx.x];
 }
 
 // Final reduction: time-step rule and monitors.  rate = (max wave + (p+1)^2 d
@@ -1137,11 +1215,10 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double* __restri
                                                           double cfl, const double* dt_fixed, double* dt,
                                                           double* t, dg2p_monitors* mon) {
   __shared__ double red[REC];
-  reduce_slots<FIN_THREADS>(rec, 0, n, red);
+  reduce_slots<REC, FIN_THREADS>(rec, 0, n, red);
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double nu = fmax(GammaEps, red[R_NU]);
-    const double rate = (red[R_WAVE] + 16.0 * dim * nu / hmin) / hmin;
+    const double rate = rate_of(red[R_WAVE], red[R_NU], GammaEps, dim, hmin);
     const double d = dt_fixed ? *dt_fixed : cfl / rate;
     if (dt) *dt = d;
     if (t) *t += d;
@@ -1155,6 +1232,21 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double* __restri
       mon->dev_u = red[R_DEVU];
       mon->nonphys = (long long)red[R_BAD];
     }
+  }
+}
+
+// Final reduction of rate records (time step only): *dt = cfl / rate (or
+// *dt_fixed), *t += dt.
+__global__ __launch_bounds__(FIN_THREADS) void k_finalize_rate(const double* __restrict__ rec, long long n,
+                                                               double GammaEps, int dim, double hmin, double cfl,
+                                                               const double* dt_fixed, double* dt, double* t) {
+  __shared__ double red[RATE];
+  reduce_slots<RATE, FIN_THREADS>(rec, 0, n, red);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double d = dt_fixed ? *dt_fixed : cfl / rate_of(red[R_WAVE], red[R_NU], GammaEps, dim, hmin);
+    *dt = d;
+    if (t) *t += d;
   }
 }
 

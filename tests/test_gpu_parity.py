@@ -220,6 +220,28 @@ def test_advance_matches_rk_steps(name, ne, steps):
         assert abs(m1["integral"][f] - m2["integral"][f]) <= 1e-13 * (abs(m2["integral"][f]) + 1e-300)
 
 
+@pytest.mark.parametrize("name,ne", [("drop2d", (136, 136)), ("rt3d", (20, 20, 12))])
+def test_advance_two_level_dt(name, ne):
+    """Grids with more than 1024 rate records reduce each step's dt in two
+    small kernels instead of inside the first stage: still the same states,
+    bit for bit, as dg2p_max_dt + dg2p_rk_step, and the same elapsed time."""
+    cfg, om, prm, U0, mesh, P = gpu_case(name, ne)
+    dg = _dg()
+    A = U0.cuda().contiguous()
+    B = A.clone()
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    last = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dg.advance(mesh, P, A, 3, cfl=0.1, t=t, dt_last=last)
+    tsum = 0.0
+    for _ in range(3):
+        dt = dg.max_dt(mesh, P, B, cfl=0.1)
+        dg.rk_step(mesh, P, B, dt)
+        tsum += float(dt.cpu())
+    assert torch.equal(A, B)
+    assert float(t.cpu()) == tsum or abs(float(t.cpu()) - tsum) <= 1e-15 * tsum
+    assert float(last.cpu()) == float(dt.cpu())
+
+
 def test_advance_fixed_dt():
     cfg, om, prm, U0, mesh, P = gpu_case("adjoint2d", (6, 6))
     dg = _dg()
