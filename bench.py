@@ -52,10 +52,10 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(workload, src_hash):
-    """HBM bytes per stage-kernel launch from the committed counter summary,
+def recorded(workload, what, key, src_hash):
+    """A figure from a committed counter summary profiles/k_stage_<workload>_<what>.md,
     if it was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"k_stage_{workload}_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"k_stage_{workload}_{what}.md")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -66,9 +66,13 @@ def recorded_traffic(workload, src_hash):
     if vals.get("source_sha256_16") != src_hash:
         return None
     try:
-        return float(vals["traffic_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
+
+
+# a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles; 1024 SIMDs at 2.4 GHz
+VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4
 
 
 def cpu_baseline(cfg, seconds):
@@ -215,11 +219,16 @@ def main():
     for name, kind in (("stage", dg2p.K_STAGE), ("ingredients", dg2p.K_INGREDIENTS),
                        ("rate", dg2p.K_RATE), ("rate_final", dg2p.K_RATE_FINAL)):
         k_ms[name] = dg2p.timing_read(kind)
-    stage_ms = k_ms["stage"][0]
+    # stage-kernel mean from the timed region: the step time less the other
+    # kernels' share (each measured by its own events), over 3 stage launches
+    # (events around every launch would add their own gaps to a ~15 us kernel)
+    other = sum(k_ms[k][0] * k_ms[k][1] for k in ("ingredients", "rate", "rate_final")) / n_prof
+    stage_ms = (ms_step - other) / 3.0
     alg_bytes = (64.0 / 3.0) * dof          # per stage launch, averaged over the 3 stages
     achieved = alg_bytes / (stage_ms * 1e-3) / 1e9
     src = source_hash()
-    traffic = recorded_traffic(args.workload, src)
+    traffic = recorded(args.workload, "traffic", "traffic_bytes_per_launch", src)
+    valu = recorded(args.workload, "valu", "valu_insts_per_launch", src)
 
     # mixed-precision forms: same workload from the same initial state
     variants = {}
@@ -334,6 +343,11 @@ def main():
             "traffic": traffic,
             "kernel": "k_stage (residual + stage combine)",
             "kernel_mean_ms": stage_ms,
+            "kernel_event_mean_ms": k_ms["stage"][0],
+            "valu_issue": None if valu is None else {
+                "insts_per_launch": valu,
+                "issue_ms": valu / VALU_ISSUE_PER_S * 1e3,
+                "frac": valu / VALU_ISSUE_PER_S * 1e3 / stage_ms},
             "algorithmic_bytes_per_launch": alg_bytes,
         },
         "kernels_mean_ms": {k: v[0] for k, v in k_ms.items()},
