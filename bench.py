@@ -25,6 +25,7 @@ The JSON line also carries
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -115,6 +116,45 @@ def cpu_baseline(cfg, seconds):
                 kind="oracle", sample=sample)
 
 
+# L1 errors of the paper's Rider-Kothe table (quadrilateral mesh, p = 3) at
+# 64^2, 128^2, 256^2 degrees of freedom, i.e. 16^2, 32^2, 64^2 elements
+PAPER_RK_L1_P3 = {16: 1.75e-2, 32: 4.83e-3, 64: 1.23e-3}
+
+
+def kinematic_section(dg2p, workloads, torch, np):
+    """Rider-Kothe single vortex, one full period, classical RK4, on the
+    library's kinematic mode at three resolutions: L1 error, relative mass
+    error and the kinematic stage throughput."""
+    rows = []
+    for N in sorted(PAPER_RK_L1_P3):
+        cfg = workloads.kinematic_config("rk2d", n_elem=(N, N))
+        mesh = dg2p.Mesh(2, (N, N), cfg["lo"], cfg["hi"])
+        phi, psi, u0 = workloads.kinematic_fields(cfg, mesh.node_coords())
+        kp = dg2p.make_kin_params(**cfg["kin"])
+        P = torch.from_numpy(np.ascontiguousarray(np.stack([phi, psi]))).cuda()
+        P0 = P[0].clone()
+        u0d = torch.from_numpy(np.ascontiguousarray(u0)).cuda()
+        dt0 = float(dg2p.kin_max_dt(mesh, kp, u0d, cfl=cfg["cfl"]).cpu())
+        ns = int(math.ceil(cfg["t_end"] / dt0))
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        dg2p.kin_rk4(mesh, kp, P, u0d, ns, 0.0, cfg["t_end"] / ns)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        e = dg2p.kin_errors(mesh, P[0].contiguous(), P0).cpu().tolist()
+        dof = 2 * mesh.E * mesh.nn
+        rows.append({"elements": [N, N], "dof": f"{4 * N}^2", "steps": ns,
+                     "l1": e[0], "l1_paper": PAPER_RK_L1_P3[N], "mass_error": e[1] / e[2],
+                     "phi_range": [float(P[0].min()), float(P[0].max())],
+                     "ms_per_step": ms / ns, "value": 4.0 * dof * ns / (ms * 1e-3)})
+    return {"workload": "rk2d: Rider-Kothe vortex, [0,1]^2 periodic, p=3, eps=h/2, Gamma=1, T=4, RK4, CFL 0.1",
+            "unit": "DOF-updates/s", "runs": rows}
+
+
 # steps after which the mixed-precision forms' field errors are stated
 ERROR_STEPS = {"shock2d": 200, "rt3d": 100}
 
@@ -163,7 +203,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip the mixed-precision and adjoint measurements")
+                    help="skip the mixed-precision, adjoint and kinematic measurements")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -307,6 +347,11 @@ def main():
                    "fd_directions": 16, "fd_step": h, "fd_max_rel_err": worst,
                    "dL_dsigma": gs}
 
+    kinematic = None
+    if not args.no_variants:
+        import numpy as np
+        kinematic = kinematic_section(dg2p, workloads, torch, np)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg, args.cpu_seconds)
@@ -353,6 +398,7 @@ def main():
         "kernels_mean_ms": {k: v[0] for k, v in k_ms.items()},
         "mixed_precision": variants,
         "adjoint": adjoint,
+        "kinematic": kinematic,
         "cpu_baseline": cpu,
         "monitors": {"nonphys": mon["nonphys"], "min_alpha": mon["min_alpha"],
                      "max_alpha": mon["max_alpha"]},

@@ -82,7 +82,10 @@ typedef enum {
   DG2P_OP_MONITORS = 3,
   DG2P_OP_RHS_VJP = 4,
   DG2P_OP_RK_STEP_VJP = 5,
-  DG2P_OP_ADVANCE = 6
+  DG2P_OP_ADVANCE = 6,
+  DG2P_OP_KIN_RHS = 7,   /* kinematic mode (dg2p_kin_workspace_size) */
+  DG2P_OP_KIN_RK4 = 8,
+  DG2P_OP_KIN_AUX = 9    /* dg2p_kin_max_dt, dg2p_kin_errors */
 } dg2p_op;
 
 /* Structured Cartesian grid of dim-dimensional tensor-product elements
@@ -224,6 +227,54 @@ int dg2p_compute_monitors(dg2p_mesh m, const dg2p_params* p /*host*/, const doub
                   double p_ref, const double* u_ref /*host, d values*/,
                   dg2p_monitors* mon /*device*/, void* work /*device*/, void* stream);
 
+/* ---- Kinematic mode ----------------------------------------------------------
+ * The phase field phi and the level set psi under a prescribed velocity
+ * u(x, t) = u0(x) s(t), s = cos(pi t / period) (period > 0) or 1 (Results,
+ * "Kinematic tests": linear advection of a droplet, Rider-Kothe vortex).
+ * Same discretisation as the alpha and psi rows of dg2p_rhs with the nodal
+ * u in place of rho u / rho; the face speed is max |u.m| over both traces
+ * (there is no sound speed), which makes the hat/tilde correction the upwind
+ * flux.  Classical RK4 in time (the paper's integrator for these tests).
+ * Periodic meshes only (EUNSUPPORTED else); FP64.
+ *   state    Phi[2][E][4^d]: Phi[0] = phi, Phi[1] = psi
+ *   velocity u0[d][E][4^d]: nodal amplitude u0 (device)                      */
+typedef struct {
+  double Gamma, eps;   /* Allen-Cahn velocity scale and thickness (Gamma >= 0, eps > 0) */
+  double c_ip;         /* interior-penalty constant (> 0) */
+  double grad_reg;     /* delta of n = g / sqrt(g.g + delta^2) (>= 0) */
+  double period;       /* T of s(t) = cos(pi t / T); <= 0: s = 1 */
+} dg2p_kin_params;
+
+/* Bytes of device workspace for op DG2P_OP_KIN_RHS, _KIN_RK4 or _KIN_AUX. */
+int dg2p_kin_workspace_size(dg2p_mesh m, int op, size_t* bytes /*host*/);
+
+/* R = dPhi/dt at time t (host scalar), [2][E][4^d]; Phi, u0, R device, R may
+ * not alias Phi.  work: DG2P_OP_KIN_RHS bytes. */
+int dg2p_kin_rhs(dg2p_mesh m, const dg2p_kin_params* kp /*host*/, const double* Phi /*device*/,
+                 const double* u0 /*device*/, double t, double* R /*device*/, void* work /*device*/,
+                 void* stream);
+
+/* n_steps classical RK4 steps in place from time t0 with the fixed step dt
+ * (host scalars; step n starts at t0 + n dt):
+ * Phi += dt/6 (k1 + 2 k2 + 2 k3 + k4), k_i = R at t, t + dt/2, t + dt/2, t + dt.
+ * work: DG2P_OP_KIN_RK4 bytes. */
+int dg2p_kin_rk4(dg2p_mesh m, const dg2p_kin_params* kp /*host*/, double* Phi /*device, in/out*/,
+                 const double* u0 /*device*/, int n_steps, double t0, double dt, void* work /*device*/,
+                 void* stream);
+
+/* Time step *dt (device scalar) = cfl h_min / (max_nodes sum_k |u0_k| +
+ * (p+1)^2 d Gamma eps / h_min): the rule of dg2p_max_dt without the sound
+ * speed.  work: DG2P_OP_KIN_AUX bytes. */
+int dg2p_kin_max_dt(dg2p_mesh m, const dg2p_kin_params* kp /*host*/, const double* u0 /*device*/, double cfl,
+                    double* dt /*device*/, void* work /*device*/, void* stream);
+
+/* GLL-quadrature integrals for the L1 error and the relative mass error of
+ * the Rider-Kothe study: out[0] = int |phi - phi0|, out[1] = int (phi - phi0),
+ * out[2] = int phi0 (device array of 3; fixed summation order).  phi, phi0:
+ * device [E][4^d].  work: DG2P_OP_KIN_AUX bytes. */
+int dg2p_kin_errors(dg2p_mesh m, const double* phi /*device*/, const double* phi0 /*device*/,
+                    double* out /*device*/, void* work /*device*/, void* stream);
+
 /* Kernel kinds of the timing facility. */
 typedef enum {
   DG2P_K_INGREDIENTS = 0, /* face-ingredient pass (neighbour interface flux / traction) */
@@ -233,7 +284,8 @@ typedef enum {
   DG2P_K_MONITOR = 4,     /* monitor reduction */
   DG2P_K_PRIM = 5,        /* initial-condition map */
   DG2P_K_VJP_LOCAL = 6,   /* adjoint: own-element reverse pass */
-  DG2P_K_VJP_GATHER = 7   /* adjoint: neighbour-contribution gather pass */
+  DG2P_K_VJP_GATHER = 7,  /* adjoint: neighbour-contribution gather pass */
+  DG2P_K_KIN_STAGE = 8    /* kinematic mode: residual + RK4 stage */
 } dg2p_kernel_kind;
 
 /* Benchmark timing.  While enabled, every kernel the library launches is

@@ -14,6 +14,7 @@
 #include "../../include/dg2p.h"
 #include "dg2p_device.hpp"
 #include "dg2p_adjoint.hpp"
+#include "dg2p_kinematic.hpp"
 
 using namespace dg2p;
 
@@ -447,6 +448,78 @@ void residual_vjp(const dg2p_mesh_s* m, const dg2p_params* p, const KArgs& A, co
   if (sigb && csf) hipLaunchKernelGGL(k_sum_add, dim3(1), dim3(BLOCK), 0, s, rec, A.nblocks, sigb);
 }
 
+// ---- kinematic mode ------------------------------------------------------------
+
+int check_kin(const dg2p_mesh_s* m, const dg2p_kin_params* kp) {
+  if (!kp) return fail(DG2P_EINVAL, "kinematic params is NULL");
+  if (!(kp->Gamma >= 0.0) || !(kp->eps > 0.0)) return fail(DG2P_EINVAL, "Gamma >= 0 and eps > 0 required");
+  if (!(kp->c_ip > 0.0)) return fail(DG2P_EINVAL, "c_ip must be > 0");
+  if (!(kp->grad_reg >= 0.0)) return fail(DG2P_EINVAL, "grad_reg must be >= 0");
+  if (!std::isfinite(kp->period)) return fail(DG2P_EINVAL, "period must be finite");
+  if (!all_periodic(m)) return fail(DG2P_EUNSUPPORTED, "the kinematic mode supports periodic meshes only");
+  return DG2P_OK;
+}
+
+KArgs kin_args(const dg2p_mesh_s* m, const dg2p_kin_params* kp) {
+  dg2p_params p;
+  std::memset(&p, 0, sizeof(p));
+  p.gamma[0] = p.gamma[1] = 2.0;  // closure constants unused by the kinematic kernels
+  p.Gamma = kp->Gamma;
+  p.eps = kp->eps;
+  p.c_ip = kp->c_ip;
+  p.grad_reg = kp->grad_reg;
+  return make_args(m, &p);
+}
+
+constexpr double PI = 3.141592653589793;
+double kin_factor(const dg2p_kin_params* kp, double t) {
+  return kp->period > 0.0 ? std::cos(PI * t / kp->period) : 1.0;
+}
+
+size_t kin_state_bytes(const dg2p_mesh_s* m) { return align256(sizeof(double) * 2 * (size_t)m->E * m->nn); }
+size_t kin_g_bytes(const dg2p_mesh_s* m) {
+  return align256(sizeof(double) * (size_t)(2 * m->dim) * (size_t)m->E * m->nfn);
+}
+long long kin_err_blocks(const dg2p_mesh_s* m) { return (m->E * m->nn + BLOCK - 1) / BLOCK; }
+size_t kin_aux_bytes(const dg2p_mesh_s* m) {
+  long long n = elem_blocks(m) * RATE;
+  const long long ne = kin_err_blocks(m) * KERR;
+  if (ne > n) n = ne;
+  return align256(sizeof(double) * (size_t)(n + RATE * REC2_MAX)) + 256;
+}
+size_t kin_work_bytes(const dg2p_mesh_s* m, int op) {
+  switch (op) {
+    case DG2P_OP_KIN_RHS: return kin_g_bytes(m);
+    case DG2P_OP_KIN_RK4: return 2 * kin_g_bytes(m) + 3 * kin_state_bytes(m);
+    case DG2P_OP_KIN_AUX: return kin_aux_bytes(m);
+    default: return 0;
+  }
+}
+
+template <int DIM>
+void kin_ingr_d(const KArgs& A, const double* P, double* G, hipStream_t s) {
+  TimedLaunch t(DG2P_K_INGREDIENTS, s);
+  hipLaunchKernelGGL(k_kin_ingredients<DIM>, elem_grid(A), dim3(BLOCK), 0, s, A, P, G);
+}
+void kin_ingr(const dg2p_mesh_s* m, const KArgs& A, const double* P, double* G, hipStream_t s) {
+  if (m->dim == 1) kin_ingr_d<1>(A, P, G, s);
+  else if (m->dim == 2) kin_ingr_d<2>(A, P, G, s);
+  else kin_ingr_d<3>(A, P, G, s);
+}
+template <int DIM>
+void kin_stage_d(int mode, const KArgs& A, const KinIO& io, hipStream_t s) {
+  TimedLaunch t(DG2P_K_KIN_STAGE, s);
+  const dim3 g = elem_grid(A), b(BLOCK);
+  if (mode == 0) hipLaunchKernelGGL((k_kin_stage<DIM, 0>), g, b, 0, s, A, io);
+  else if (mode == 1) hipLaunchKernelGGL((k_kin_stage<DIM, 1>), g, b, 0, s, A, io);
+  else hipLaunchKernelGGL((k_kin_stage<DIM, 2>), g, b, 0, s, A, io);
+}
+void kin_stage(const dg2p_mesh_s* m, int mode, const KArgs& A, const KinIO& io, hipStream_t s) {
+  if (m->dim == 1) kin_stage_d<1>(mode, A, io, s);
+  else if (m->dim == 2) kin_stage_d<2>(mode, A, io, s);
+  else kin_stage_d<3>(mode, A, io, s);
+}
+
 }  // namespace
 
 extern "C" {
@@ -819,6 +892,124 @@ int dg2p_rk_step_vjp(dg2p_mesh m, const dg2p_params* p, const double* U_n, const
   hipLaunchKernelGGL(k_vjp_combine, dim3(eb), dim3(256), 0, s, n, B, dt, 1.0, 0, U_n_bar, 0.0, nullptr, 1.0, Rb);
   residual_vjp(m, p, A, U_n, GA, Rb, T, FB, rec, U_n_bar, 1, param_bar, s);
   return hip_check(hipGetLastError(), "rk_step_vjp launch");
+}
+
+int dg2p_kin_workspace_size(dg2p_mesh m, int op, size_t* bytes) {
+  g_last_error.clear();
+  if (!m || !bytes) return fail(DG2P_EINVAL, "mesh and bytes must be non-NULL");
+  if (op < DG2P_OP_KIN_RHS || op > DG2P_OP_KIN_AUX) return fail(DG2P_EINVAL, "not a kinematic op");
+  *bytes = kin_work_bytes(m, op);
+  return DG2P_OK;
+}
+
+int dg2p_kin_rhs(dg2p_mesh m, const dg2p_kin_params* kp, const double* Phi, const double* u0, double t, double* R,
+                 void* work, void* stream) {
+  g_last_error.clear();
+  if (!m || !Phi || !u0 || !R) return fail(DG2P_EINVAL, "mesh, Phi, u0 and R must be non-NULL");
+  if (R == Phi) return fail(DG2P_EINVAL, "R may not alias Phi");
+  int st = check_kin(m, kp);
+  if (st) return st;
+  st = check_ws(work, kin_work_bytes(m, DG2P_OP_KIN_RHS));
+  if (st) return st;
+  const KArgs A = kin_args(m, kp);
+  hipStream_t s = (hipStream_t)stream;
+  double* G = static_cast<double*>(work);
+  kin_ingr(m, A, Phi, G, s);
+  KinIO io{};
+  io.Ps = Phi;
+  io.Gin = G;
+  io.u0 = u0;
+  io.s = kin_factor(kp, t);
+  io.Out = R;
+  kin_stage(m, 0, A, io, s);
+  return hip_check(hipGetLastError(), "kin_rhs launch");
+}
+
+int dg2p_kin_rk4(dg2p_mesh m, const dg2p_kin_params* kp, double* Phi, const double* u0, int n_steps, double t0,
+                 double dt, void* work, void* stream) {
+  g_last_error.clear();
+  if (!m || !Phi || !u0) return fail(DG2P_EINVAL, "mesh, Phi and u0 must be non-NULL");
+  if (n_steps < 0) return fail(DG2P_EINVAL, "n_steps must be >= 0");
+  if (!std::isfinite(dt) || !std::isfinite(t0)) return fail(DG2P_EINVAL, "t0 and dt must be finite");
+  int st = check_kin(m, kp);
+  if (st) return st;
+  st = check_ws(work, kin_work_bytes(m, DG2P_OP_KIN_RK4));
+  if (st) return st;
+  const KArgs A = kin_args(m, kp);
+  hipStream_t s = (hipStream_t)stream;
+  const size_t gb = kin_g_bytes(m), sb = kin_state_bytes(m);
+  char* c = static_cast<char*>(work);
+  double* G0 = reinterpret_cast<double*>(c); c += gb;
+  double* G1 = reinterpret_cast<double*>(c); c += gb;
+  double* S1 = reinterpret_cast<double*>(c); c += sb;
+  double* S2 = reinterpret_cast<double*>(c); c += sb;
+  double* Acc = reinterpret_cast<double*>(c);
+  if (n_steps > 0) kin_ingr(m, A, Phi, G0, s);
+  for (int it = 0; it < n_steps; ++it) {
+    const double t = t0 + it * dt;
+    KinIO io{};
+    io.u0 = u0;
+    io.Pn = Phi;
+    io.Acc = Acc;
+    // k1 at t: Acc = k1, S1 = Phi + dt/2 k1
+    io.Ps = Phi; io.Gin = G0; io.s = kin_factor(kp, t); io.Out = S1; io.Gout = G1;
+    io.cdt = 0.5 * dt; io.wacc = 1.0; io.acc_first = 1;
+    kin_stage(m, 1, A, io, s);
+    // k2 at t + dt/2: Acc += 2 k2, S2 = Phi + dt/2 k2
+    io.Ps = S1; io.Gin = G1; io.s = kin_factor(kp, t + 0.5 * dt); io.Out = S2; io.Gout = G0;
+    io.cdt = 0.5 * dt; io.wacc = 2.0; io.acc_first = 0;
+    kin_stage(m, 1, A, io, s);
+    // k3 at t + dt/2: Acc += 2 k3, S1 = Phi + dt k3
+    io.Ps = S2; io.Gin = G0; io.Out = S1; io.Gout = G1;
+    io.cdt = dt;
+    kin_stage(m, 1, A, io, s);
+    // k4 at t + dt: Phi += dt/6 (Acc + k4)
+    io.Ps = S1; io.Gin = G1; io.s = kin_factor(kp, t + dt); io.Out = Phi; io.Gout = G0;
+    io.dt6 = dt / 6.0;
+    kin_stage(m, 2, A, io, s);
+  }
+  return hip_check(hipGetLastError(), "kin_rk4 launch");
+}
+
+int dg2p_kin_max_dt(dg2p_mesh m, const dg2p_kin_params* kp, const double* u0, double cfl, double* dt, void* work,
+                    void* stream) {
+  g_last_error.clear();
+  if (!m || !u0 || !dt) return fail(DG2P_EINVAL, "mesh, u0 and dt must be non-NULL");
+  if (!(cfl > 0.0)) return fail(DG2P_EINVAL, "cfl must be > 0");
+  int st = check_kin(m, kp);
+  if (st) return st;
+  st = check_ws(work, kin_work_bytes(m, DG2P_OP_KIN_AUX));
+  if (st) return st;
+  const KArgs A = kin_args(m, kp);
+  hipStream_t s = (hipStream_t)stream;
+  Work w;
+  w.rec = static_cast<double*>(work);
+  w.rec2 = w.rec + RATE * elem_blocks(m);
+  {
+    TimedLaunch t(DG2P_K_RATE, s);
+    if (m->dim == 1) hipLaunchKernelGGL(k_kin_rate<1>, elem_grid(A), dim3(BLOCK), 0, s, A, u0, w.rec);
+    else if (m->dim == 2) hipLaunchKernelGGL(k_kin_rate<2>, elem_grid(A), dim3(BLOCK), 0, s, A, u0, w.rec);
+    else hipLaunchKernelGGL(k_kin_rate<3>, elem_grid(A), dim3(BLOCK), 0, s, A, u0, w.rec);
+  }
+  finalize_rate(m, A, w, elem_blocks(m), cfl, nullptr, dt, nullptr, s);
+  return hip_check(hipGetLastError(), "kin_max_dt launch");
+}
+
+int dg2p_kin_errors(dg2p_mesh m, const double* phi, const double* phi0, double* out, void* work, void* stream) {
+  g_last_error.clear();
+  if (!m || !phi || !phi0 || !out) return fail(DG2P_EINVAL, "mesh, phi, phi0 and out must be non-NULL");
+  int st = check_ws(work, kin_work_bytes(m, DG2P_OP_KIN_AUX));
+  if (st) return st;
+  dg2p_kin_params kp{1.0, 1.0, 1.0, 0.0, 0.0};
+  const KArgs A = kin_args(m, &kp);
+  hipStream_t s = (hipStream_t)stream;
+  double* rec = static_cast<double*>(work);
+  const long long nb = kin_err_blocks(m);
+  if (m->dim == 1) hipLaunchKernelGGL(k_kin_errors<1>, dim3((unsigned)nb), dim3(BLOCK), 0, s, A, phi, phi0, rec);
+  else if (m->dim == 2) hipLaunchKernelGGL(k_kin_errors<2>, dim3((unsigned)nb), dim3(BLOCK), 0, s, A, phi, phi0, rec);
+  else hipLaunchKernelGGL(k_kin_errors<3>, dim3((unsigned)nb), dim3(BLOCK), 0, s, A, phi, phi0, rec);
+  hipLaunchKernelGGL(k_kin_sum, dim3(1), dim3(FIN_THREADS), 0, s, rec, nb, 3, out);
+  return hip_check(hipGetLastError(), "kin_errors launch");
 }
 
 int dg2p_timing_enable(int on) {

@@ -25,6 +25,7 @@ OK, EINVAL, EHIP, ENONPHYS, EUNSUPPORTED, EWORKSPACE = 0, -1, -2, -3, -4, -5
 BC = {"periodic": 0, "slip_wall": 1, "dirichlet": 2, "extrapolate": 3}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
 OP_RHS, OP_RK_STEP, OP_MAX_DT, OP_MONITORS, OP_RHS_VJP, OP_RK_STEP_VJP, OP_ADVANCE = range(7)
+OP_KIN_RHS, OP_KIN_RK4, OP_KIN_AUX = 7, 8, 9
 
 
 class MeshDesc(ctypes.Structure):
@@ -33,6 +34,11 @@ class MeshDesc(ctypes.Structure):
                 ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
                 ("bc", (ctypes.c_int * 2) * 3),
                 ("bc_state", ((ctypes.c_double * 8) * 2) * 3)]
+
+
+class KinParams(ctypes.Structure):
+    _fields_ = [("Gamma", ctypes.c_double), ("eps", ctypes.c_double), ("c_ip", ctypes.c_double),
+                ("grad_reg", ctypes.c_double), ("period", ctypes.c_double)]
 
 
 class Params(ctypes.Structure):
@@ -73,10 +79,15 @@ _SIG = {
     "dg2p_rk_step_vjp": ([_vp, ctypes.POINTER(Params), _dp, _dp, _dp, _dp, _dp, _vp, _vp], _i),
     "dg2p_prim_to_cons_vjp": ([_vp, ctypes.POINTER(Params), _dp, _dp, _dp, _vp], _i),
     "dg2p_node_weights": ([_vp, _dp], _i),
+    "dg2p_kin_workspace_size": ([_vp, _i, ctypes.POINTER(ctypes.c_size_t)], _i),
+    "dg2p_kin_rhs": ([_vp, ctypes.POINTER(KinParams), _dp, _dp, _d, _dp, _vp, _vp], _i),
+    "dg2p_kin_rk4": ([_vp, ctypes.POINTER(KinParams), _dp, _dp, _i, _d, _d, _vp, _vp], _i),
+    "dg2p_kin_max_dt": ([_vp, ctypes.POINTER(KinParams), _dp, _d, _dp, _vp, _vp], _i),
+    "dg2p_kin_errors": ([_vp, _dp, _dp, _dp, _vp, _vp], _i),
     "dg2p_timing_enable": ([_i], _i),
     "dg2p_timing_read": ([_i, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_longlong)], _i),
 }
-K_INGREDIENTS, K_STAGE, K_RATE, K_RATE_FINAL, K_MONITOR, K_PRIM, K_VJP_LOCAL, K_VJP_GATHER = range(8)
+K_INGREDIENTS, K_STAGE, K_RATE, K_RATE_FINAL, K_MONITOR, K_PRIM, K_VJP_LOCAL, K_VJP_GATHER, K_KIN_STAGE = range(9)
 for _name, (_args, _res) in _SIG.items():
     _fn = getattr(_lib, _name)
     _fn.argtypes = _args
@@ -189,7 +200,12 @@ class Mesh:
 
     def workspace(self, params, op, device):
         """Device workspace for an operation (cached per op, grown on demand)."""
-        need = self.workspace_bytes(params, op)
+        if op >= OP_KIN_RHS:
+            n = ctypes.c_size_t()
+            _check(_lib.dg2p_kin_workspace_size(self._h, op, ctypes.byref(n)), "dg2p_kin_workspace_size")
+            need = n.value
+        else:
+            need = self.workspace_bytes(params, op)
         key = (op, str(device))
         buf = self._ws.get(key)
         if buf is None or buf.numel() < need + 256:
@@ -344,3 +360,60 @@ def prim_tensor(pf, d, device="cuda"):
     arrs = [pf["alpha"], pf["psi"], pf["rho1"], pf["rho2"]] + [pf["u"][j] for j in range(d)] + [pf["P"]]
     host = np.stack([np.ascontiguousarray(a, dtype=np.float64) for a in arrs])
     return torch.from_numpy(host).to(device)
+
+
+# ---- kinematic mode: phi and psi under a prescribed velocity u0(x) s(t) -------------
+def make_kin_params(Gamma=1.0, eps=0.01, c_ip=1.0, grad_reg=1e-12, period=0.0):
+    return KinParams(float(Gamma), float(eps), float(c_ip), float(grad_reg), float(period))
+
+
+def _as_kin(mesh, t, rows, what):
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous float64 CUDA tensor")
+    if tuple(t.shape) != (rows, mesh.E, mesh.nn):
+        raise ValueError(f"{what} shape {tuple(t.shape)} != {(rows, mesh.E, mesh.nn)}")
+    return t
+
+
+def kin_rhs(mesh, kp, Phi, u0, t, out=None, stream=None):
+    """R = dPhi/dt at time t; Phi [2, E, nn] (phi, psi), u0 [d, E, nn]."""
+    Phi = _as_kin(mesh, Phi, 2, "Phi")
+    u0 = _as_kin(mesh, u0, mesh.dim, "u0")
+    R = torch.empty_like(Phi) if out is None else out
+    ws = mesh.workspace(None, OP_KIN_RHS, Phi.device)
+    _check(_lib.dg2p_kin_rhs(mesh.handle, ctypes.byref(kp), _ptr(Phi), _ptr(u0), float(t), _ptr(R), ws,
+                             _stream(stream)), "dg2p_kin_rhs")
+    return R
+
+
+def kin_rk4(mesh, kp, Phi, u0, n_steps, t0, dt, stream=None):
+    """n_steps classical RK4 steps in place from t0 with fixed dt (host scalars)."""
+    Phi = _as_kin(mesh, Phi, 2, "Phi")
+    u0 = _as_kin(mesh, u0, mesh.dim, "u0")
+    ws = mesh.workspace(None, OP_KIN_RK4, Phi.device)
+    _check(_lib.dg2p_kin_rk4(mesh.handle, ctypes.byref(kp), _ptr(Phi), _ptr(u0), int(n_steps), float(t0),
+                             float(dt), ws, _stream(stream)), "dg2p_kin_rk4")
+    return Phi
+
+
+def kin_max_dt(mesh, kp, u0, cfl=0.1, stream=None):
+    """Device scalar dt of the kinematic time-step rule."""
+    u0 = _as_kin(mesh, u0, mesh.dim, "u0")
+    dt = torch.empty(1, dtype=torch.float64, device=u0.device)
+    ws = mesh.workspace(None, OP_KIN_AUX, u0.device)
+    _check(_lib.dg2p_kin_max_dt(mesh.handle, ctypes.byref(kp), _ptr(u0), float(cfl), _ptr(dt), ws,
+                                _stream(stream)), "dg2p_kin_max_dt")
+    return dt
+
+
+def kin_errors(mesh, phi, phi0, stream=None):
+    """(int |phi - phi0|, int (phi - phi0), int phi0) as a device tensor of 3."""
+    for t, w in ((phi, "phi"), (phi0, "phi0")):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or \
+                tuple(t.shape) != (mesh.E, mesh.nn):
+            raise ValueError(f"{w} must be a contiguous float64 CUDA tensor of shape (E, nn)")
+    out = torch.empty(3, dtype=torch.float64, device=phi.device)
+    ws = mesh.workspace(None, OP_KIN_AUX, phi.device)
+    _check(_lib.dg2p_kin_errors(mesh.handle, _ptr(phi), _ptr(phi0), _ptr(out), ws, _stream(stream)),
+           "dg2p_kin_errors")
+    return out

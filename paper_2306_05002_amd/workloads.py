@@ -212,3 +212,49 @@ def fd_direction(shape_u, k):
     du = rng.standard_normal(shape_u)
     ds = float(rng.standard_normal())
     return du, ds
+
+
+# ---- kinematic mode (phase field and level set under a prescribed velocity) ----------
+KIN_NAMES = ("rk2d", "adv2d")
+KIN_FULL_ELEMS = {"rk2d": (16, 16), "adv2d": (16, 16)}
+
+
+def kinematic_config(name, n_elem=None):
+    """Kinematic test cases of the Results section, p = 3 on [0,1]^2, periodic.
+
+    rk2d   Rider-Kothe single vortex: droplet R = 0.15 at (0.5, 0.75),
+           u = (sin^2(pi x) sin(2 pi y), -sin(2 pi x) sin^2(pi y)) cos(pi t / 4),
+           one period T = 4, Gamma = 1, eps = h / 2 (half the element size,
+           i.e. two nodal spacings at p = 3)
+    adv2d  linear advection of a droplet R = 0.15 at (0.5, 0.5) by u = (1, 0)
+           for one period, fixed eps = 0.05, Gamma = 1
+    """
+    if name not in KIN_NAMES:
+        raise KeyError(name)
+    n_elem = tuple(n_elem) if n_elem is not None else KIN_FULL_ELEMS[name]
+    h = 1.0 / n_elem[0]
+    cfg = dict(name=name, dim=2, order=ORDER, n_elem=n_elem, lo=(0.0, 0.0), hi=(1.0, 1.0),
+               bc=[("periodic", "periodic")] * 2, cfl=0.1)
+    if name == "rk2d":
+        cfg.update(kin=dict(Gamma=1.0, eps=0.5 * h, c_ip=1.0, grad_reg=1e-12, period=4.0),
+                   t_end=4.0, centre=(0.5, 0.75))
+    else:
+        cfg.update(kin=dict(Gamma=1.0, eps=0.05, c_ip=1.0, grad_reg=1e-12, period=0.0),
+                   t_end=1.0, centre=(0.5, 0.5))
+    return cfg
+
+
+def kinematic_fields(cfg, X):
+    """(phi, psi, u0) at node coordinates X [2, ...]: phi = 1/(1 + exp(-psi/eps))
+    with psi = R - r the signed distance to the droplet rim (positive inside)."""
+    x, y = X[0], X[1]
+    cx, cy = cfg["centre"]
+    eps = cfg["kin"]["eps"]
+    psi = 0.15 - np.sqrt((x - cx) ** 2 + (y - cy) ** 2)
+    phi = _sigmoid(psi / eps)
+    if cfg["name"] == "rk2d":
+        u0 = np.stack([np.sin(math.pi * x) ** 2 * np.sin(2 * math.pi * y),
+                       -np.sin(2 * math.pi * x) * np.sin(math.pi * y) ** 2])
+    else:
+        u0 = np.stack([np.ones_like(x), np.zeros_like(x)])
+    return phi, psi, u0

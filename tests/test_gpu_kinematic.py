@@ -1,0 +1,138 @@
+"""Kinematic mode on the GPU (through the C ABI) against the oracle: the
+phase-field / level-set residual under a prescribed velocity, classical RK4
+steps, the time-step rule and the L1 / mass-error integrals; and a full
+Rider-Kothe period against the oracle's stored run.  Parity bar as for the
+full residual: 1e-12 relative per field."""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import kinematic as K
+from paper_2306_05002_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _dg():
+    from paper_2306_05002_amd import dg2p
+    return dg2p
+
+
+def _T(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64)
+
+
+def case(name, ne):
+    """(oracle mesh, KinParams, Phi0, u0, library mesh, library params) of a
+    kinematic workload, or of a d-dimensional constant-velocity slab/box."""
+    dg = _dg()
+    if name in workloads.KIN_NAMES:
+        cfg = workloads.kinematic_config(name, n_elem=ne)
+        om = oracle.OracleMesh(2, 3, ne, cfg["lo"], cfg["hi"], cfg["bc"])
+        phi, psi, u0 = workloads.kinematic_fields(cfg, om.node_coords().numpy())
+        kin = cfg["kin"]
+    else:  # "box<d>": smooth periodic fields, uniform velocity
+        d = len(ne)
+        om = oracle.OracleMesh(d, 3, ne, (0.0,) * d, (1.0,) * d)
+        X = om.node_coords().numpy()
+        psi = 0.2 * np.prod([np.cos(2 * math.pi * X[k]) for k in range(d)], axis=0) + 0.05
+        kin = dict(Gamma=0.8, eps=0.03, c_ip=1.0, grad_reg=1e-12, period=0.0)
+        phi = 1.0 / (1.0 + np.exp(-psi / kin["eps"]))
+        u0 = np.stack([np.full_like(psi, (0.7, -0.4, 0.3)[k]) for k in range(d)])
+    kp = K.KinParams(**kin)
+    mesh = dg.Mesh(om.d, ne, om.lo, om.hi)
+    lkp = dg.make_kin_params(**kin)
+    return om, kp, torch.stack([_T(phi), _T(psi)]), _T(u0), mesh, lkp
+
+
+def rel_err(a, b):
+    return [float((a[f] - b[f]).abs().max()) / max(float(b[f].abs().max()), 1e-300) for f in range(a.shape[0])]
+
+
+KIN_RHS = [("rk2d", (16, 16), 0.7), ("rk2d", (5, 3), 1.3), ("rk2d", (1, 1), 0.0), ("adv2d", (8, 8), 0.2),
+           ("box1", (13,), 0.0), ("box3", (3, 2, 4), 0.0)]
+
+
+@pytest.mark.parametrize("name,ne,t", KIN_RHS)
+def test_kin_rhs_parity(name, ne, t):
+    om, kp, Phi, u0, mesh, lkp = case(name, ne)
+    Ro = K.kin_rhs(Phi, K.velocity(u0, t, kp), om, kp)
+    Rg = _dg().kin_rhs(mesh, lkp, Phi.cuda(), u0.cuda(), t).cpu()
+    errs = rel_err(Rg, Ro)
+    print(name, ne, ["%.1e" % e for e in errs])
+    assert max(errs) <= TOL, errs
+
+
+@pytest.mark.parametrize("name,ne", [("rk2d", (6, 5)), ("adv2d", (7, 4)), ("box3", (2, 3, 2))])
+def test_kin_rk4_parity(name, ne):
+    om, kp, Phi, u0, mesh, lkp = case(name, ne)
+    dt, t0, n = 0.002, 0.4, 4
+    Po = Phi
+    for s in range(n):
+        Po = K.rk4_step(Po, t0 + s * dt, dt, u0, om, kp)
+    Pg = Phi.cuda().contiguous()
+    _dg().kin_rk4(mesh, lkp, Pg, u0.cuda(), n, t0, dt)
+    errs = rel_err(Pg.cpu(), Po)
+    assert max(errs) <= TOL, errs
+
+
+@pytest.mark.parametrize("name,ne", [("rk2d", (16, 16)), ("rk2d", (7, 9)), ("box1", (10,))])
+def test_kin_max_dt_and_errors(name, ne):
+    om, kp, Phi, u0, mesh, lkp = case(name, ne)
+    dg = _dg()
+    dtg = float(dg.kin_max_dt(mesh, lkp, u0.cuda(), cfl=0.1).cpu())
+    dto = K.max_dt(u0, om, kp, cfl=0.1)
+    assert abs(dtg - dto) <= 1e-15 * dto
+    phi1 = Phi[0] + 1e-3 * torch.sin(7.0 * Phi[1])
+    e = dg.kin_errors(mesh, phi1.cuda().contiguous(), Phi[0].cuda().contiguous()).cpu()
+    W = om.node_weights()
+    want = [K.l1_error(phi1, Phi[0], om), float(((phi1 - Phi[0]) * W).sum()), float((Phi[0] * W).sum())]
+    for a, b in zip(e.tolist(), want):
+        assert abs(a - b) <= 1e-13 * max(abs(b), float((Phi[0].abs() * W).sum()) * 1e-3)
+
+
+def test_kin_rejects_unsupported():
+    dg = _dg()
+    mesh = dg.Mesh(2, (4, 4), (0, 0), (1, 1), bc=[("slip_wall", "slip_wall"), ("periodic", "periodic")])
+    Phi = torch.zeros(2, mesh.E, mesh.nn, dtype=torch.float64, device="cuda")
+    u0 = torch.zeros(2, mesh.E, mesh.nn, dtype=torch.float64, device="cuda")
+    with pytest.raises(dg.Dg2pError) as ei:
+        dg.kin_rhs(mesh, dg.make_kin_params(), Phi, u0, 0.0)
+    assert ei.value.status == dg.EUNSUPPORTED
+    mp = dg.Mesh(2, (4, 4), (0, 0), (1, 1))
+    with pytest.raises(dg.Dg2pError) as ei:
+        dg.kin_rhs(mp, dg.make_kin_params(eps=0.0), Phi, u0, 0.0)
+    assert ei.value.status == dg.EINVAL
+
+
+def test_rider_kothe_full_period_matches_oracle_run():
+    """One full Rider-Kothe period at 16 x 16 p3 (64^2 DOF, ~11 000 RK4
+    steps) on the GPU against the oracle's stored run of the same problem
+    (tests/golden/rk2d_16x16_p3.json, written by make_kinematic_golden.py)."""
+    path = os.path.join(HERE, "golden", "rk2d_16x16_p3.json")
+    if not os.path.exists(path):
+        pytest.skip("oracle golden run not generated")
+    gold = json.load(open(path))
+    om, kp, Phi, u0, mesh, lkp = case("rk2d", (16, 16))
+    dg = _dg()
+    u0d = u0.cuda()
+    dt0 = float(dg.kin_max_dt(mesh, lkp, u0d, cfl=0.1).cpu())
+    ns = int(math.ceil(4.0 / dt0))
+    assert ns == gold["steps"]
+    P = Phi.cuda().contiguous()
+    P0 = P[0].clone()
+    dg.kin_rk4(mesh, lkp, P, u0d, ns, 0.0, 4.0 / ns)
+    e = dg.kin_errors(mesh, P[0].contiguous(), P0).cpu().tolist()
+    l1, em = e[0], e[1] / e[2]
+    print("L1", l1, gold["l1"], "E_m", em, gold["mass_error"])
+    assert abs(l1 - gold["l1"]) <= 1e-9 * gold["l1"]
+    assert abs(em - gold["mass_error"]) <= 1e-6 * abs(gold["mass_error"]) + 1e-13
