@@ -121,36 +121,21 @@ def cpu_baseline(cfg, seconds):
 PAPER_RK_L1_P3 = {16: 1.75e-2, 32: 4.83e-3, 64: 1.23e-3}
 
 
-def kinematic_section(dg2p, workloads, torch, np):
+def kinematic_section():
     """Rider-Kothe single vortex, one full period, classical RK4, on the
-    library's kinematic mode at three resolutions: L1 error, relative mass
-    error and the kinematic stage throughput."""
+    library's kinematic mode at three resolutions, without and with the
+    level-set re-initialisation (50 pseudo-time iterations every 2000 steps):
+    L1 error, relative mass error and the kinematic stage throughput."""
+    from paper_2306_05002_amd import kinematic
     rows = []
     for N in sorted(PAPER_RK_L1_P3):
-        cfg = workloads.kinematic_config("rk2d", n_elem=(N, N))
-        mesh = dg2p.Mesh(2, (N, N), cfg["lo"], cfg["hi"])
-        phi, psi, u0 = workloads.kinematic_fields(cfg, mesh.node_coords())
-        kp = dg2p.make_kin_params(**cfg["kin"])
-        P = torch.from_numpy(np.ascontiguousarray(np.stack([phi, psi]))).cuda()
-        P0 = P[0].clone()
-        u0d = torch.from_numpy(np.ascontiguousarray(u0)).cuda()
-        dt0 = float(dg2p.kin_max_dt(mesh, kp, u0d, cfl=cfg["cfl"]).cpu())
-        ns = int(math.ceil(cfg["t_end"] / dt0))
-        stream = torch.cuda.current_stream()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        dg2p.kin_rk4(mesh, kp, P, u0d, ns, 0.0, cfg["t_end"] / ns)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        e = dg2p.kin_errors(mesh, P[0].contiguous(), P0).cpu().tolist()
-        dof = 2 * mesh.E * mesh.nn
-        rows.append({"elements": [N, N], "dof": f"{4 * N}^2", "steps": ns,
-                     "l1": e[0], "l1_paper": PAPER_RK_L1_P3[N], "mass_error": e[1] / e[2],
-                     "phi_range": [float(P[0].min()), float(P[0].max())],
-                     "ms_per_step": ms / ns, "value": 4.0 * dof * ns / (ms * 1e-3)})
+        r0 = kinematic.rider_kothe(N, time_it=True)
+        r1 = kinematic.rider_kothe(N, reinit_every=2000)
+        rows.append({"elements": [N, N], "dof": f"{4 * N}^2", "steps": r0["steps"],
+                     "l1": r0["l1"], "l1_reinit": r1["l1"], "l1_paper": PAPER_RK_L1_P3[N],
+                     "mass_error": r0["mass_error"], "mass_error_reinit": r1["mass_error"],
+                     "reinit_calls": r1["reinit"], "ms_per_step": r0["ms"] / r0["steps"],
+                     "value": 4.0 * r0["dof"] * r0["steps"] / (r0["ms"] * 1e-3)})
     return {"workload": "rk2d: Rider-Kothe vortex, [0,1]^2 periodic, p=3, eps=h/2, Gamma=1, T=4, RK4, CFL 0.1",
             "unit": "DOF-updates/s", "runs": rows}
 
@@ -349,8 +334,7 @@ def main():
 
     kinematic = None
     if not args.no_variants:
-        import numpy as np
-        kinematic = kinematic_section(dg2p, workloads, torch, np)
+        kinematic = kinematic_section()
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -245,7 +245,8 @@ typedef struct {
   double period;       /* T of s(t) = cos(pi t / T); <= 0: s = 1 */
 } dg2p_kin_params;
 
-/* Bytes of device workspace for op DG2P_OP_KIN_RHS, _KIN_RK4 or _KIN_AUX. */
+/* Bytes of device workspace for op DG2P_OP_KIN_RHS, _KIN_RK4 (also
+ * dg2p_kin_reinit) or _KIN_AUX. */
 int dg2p_kin_workspace_size(dg2p_mesh m, int op, size_t* bytes /*host*/);
 
 /* R = dPhi/dt at time t (host scalar), [2][E][4^d]; Phi, u0, R device, R may
@@ -261,6 +262,18 @@ int dg2p_kin_rhs(dg2p_mesh m, const dg2p_kin_params* kp /*host*/, const double* 
 int dg2p_kin_rk4(dg2p_mesh m, const dg2p_kin_params* kp /*host*/, double* Phi /*device, in/out*/,
                  const double* u0 /*device*/, int n_steps, double t0, double dt, void* work /*device*/,
                  void* stream);
+
+/* Level-set re-initialisation in place (closing paragraphs of the Section
+ * "Discontinuous Galerkin discretisation"): Phi[1] (psi) is replaced by n_iter
+ * classical RK4 pseudo-time steps of length dtau of
+ *   d psi / d tau = sgn (1 - |grad psi|) + div(nu grad psi)
+ * started from psi0 = Phi[0] - 1/2, with sgn = tanh(psi0 / (2 eps |grad psi0|))
+ * (|grad psi0| regularised by grad_reg) and the diffusive flux discretised
+ * with the symmetric interior penalty (coefficient nu, penalty
+ * c_ip nu (p+1)^2 / h).  The source sign is the one that relaxes |grad psi|
+ * towards 1.  Phi[0] is unchanged.  work: DG2P_OP_KIN_RK4 bytes. */
+int dg2p_kin_reinit(dg2p_mesh m, const dg2p_kin_params* kp /*host*/, double* Phi /*device, in/out*/, int n_iter,
+                    double nu, double dtau, void* work /*device*/, void* stream);
 
 /* Time step *dt (device scalar) = cfl h_min / (max_nodes sum_k |u0_k| +
  * (p+1)^2 d Gamma eps / h_min): the rule of dg2p_max_dt without the sound

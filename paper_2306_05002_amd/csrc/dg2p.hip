@@ -490,7 +490,7 @@ size_t kin_aux_bytes(const dg2p_mesh_s* m) {
 size_t kin_work_bytes(const dg2p_mesh_s* m, int op) {
   switch (op) {
     case DG2P_OP_KIN_RHS: return kin_g_bytes(m);
-    case DG2P_OP_KIN_RK4: return 2 * kin_g_bytes(m) + 3 * kin_state_bytes(m);
+    case DG2P_OP_KIN_RK4: return 2 * kin_g_bytes(m) + 3 * kin_state_bytes(m) + kin_state_bytes(m) / 2 + 256;
     case DG2P_OP_KIN_AUX: return kin_aux_bytes(m);
     default: return 0;
   }
@@ -518,6 +518,19 @@ void kin_stage(const dg2p_mesh_s* m, int mode, const KArgs& A, const KinIO& io, 
   if (m->dim == 1) kin_stage_d<1>(mode, A, io, s);
   else if (m->dim == 2) kin_stage_d<2>(mode, A, io, s);
   else kin_stage_d<3>(mode, A, io, s);
+}
+
+template <int DIM>
+void reinit_stage_d(int mode, const KArgs& A, const ReinitIO& io, hipStream_t s) {
+  TimedLaunch t(DG2P_K_KIN_STAGE, s);
+  const dim3 g = elem_grid(A), b(BLOCK);
+  if (mode == 1) hipLaunchKernelGGL((k_reinit_stage<DIM, 1>), g, b, 0, s, A, io);
+  else hipLaunchKernelGGL((k_reinit_stage<DIM, 2>), g, b, 0, s, A, io);
+}
+void reinit_stage(const dg2p_mesh_s* m, int mode, const KArgs& A, const ReinitIO& io, hipStream_t s) {
+  if (m->dim == 1) reinit_stage_d<1>(mode, A, io, s);
+  else if (m->dim == 2) reinit_stage_d<2>(mode, A, io, s);
+  else reinit_stage_d<3>(mode, A, io, s);
 }
 
 }  // namespace
@@ -969,6 +982,57 @@ int dg2p_kin_rk4(dg2p_mesh m, const dg2p_kin_params* kp, double* Phi, const doub
     kin_stage(m, 2, A, io, s);
   }
   return hip_check(hipGetLastError(), "kin_rk4 launch");
+}
+
+int dg2p_kin_reinit(dg2p_mesh m, const dg2p_kin_params* kp, double* Phi, int n_iter, double nu, double dtau,
+                    void* work, void* stream) {
+  g_last_error.clear();
+  if (!m || !Phi) return fail(DG2P_EINVAL, "mesh and Phi must be non-NULL");
+  if (n_iter < 0) return fail(DG2P_EINVAL, "n_iter must be >= 0");
+  if (!(nu > 0.0) || !std::isfinite(nu) || !std::isfinite(dtau)) return fail(DG2P_EINVAL, "nu > 0, finite dtau");
+  int st = check_kin(m, kp);
+  if (st) return st;
+  st = check_ws(work, kin_work_bytes(m, DG2P_OP_KIN_RK4));
+  if (st) return st;
+  // the SIPG coefficient of the diffusive flux is nu: Gamma eps := 1 * nu
+  dg2p_kin_params kd = *kp;
+  kd.Gamma = 1.0;
+  kd.eps = nu;
+  const KArgs A = kin_args(m, &kd);
+  hipStream_t s = (hipStream_t)stream;
+  const size_t gb = kin_g_bytes(m), sb = kin_state_bytes(m);
+  char* c = static_cast<char*>(work);
+  double* G0 = reinterpret_cast<double*>(c); c += gb;
+  double* G1 = reinterpret_cast<double*>(c); c += gb;
+  double* S1 = reinterpret_cast<double*>(c); c += sb;
+  double* S2 = reinterpret_cast<double*>(c); c += sb;
+  double* Acc = reinterpret_cast<double*>(c); c += sb;
+  double* sgn = reinterpret_cast<double*>(c);
+  double* psi = Phi + (size_t)m->E * m->nn;
+  {
+    TimedLaunch t(DG2P_K_INGREDIENTS, s);
+    if (m->dim == 1)
+      hipLaunchKernelGGL(k_reinit_start<1>, elem_grid(A), dim3(BLOCK), 0, s, A, Phi, kp->eps, psi, sgn, G0);
+    else if (m->dim == 2)
+      hipLaunchKernelGGL(k_reinit_start<2>, elem_grid(A), dim3(BLOCK), 0, s, A, Phi, kp->eps, psi, sgn, G0);
+    else
+      hipLaunchKernelGGL(k_reinit_start<3>, elem_grid(A), dim3(BLOCK), 0, s, A, Phi, kp->eps, psi, sgn, G0);
+  }
+  for (int it = 0; it < n_iter; ++it) {
+    ReinitIO io{};
+    io.sgn = sgn;
+    io.Pn = psi;
+    io.Acc = Acc;
+    io.Ps = psi; io.Gin = G0; io.Out = S1; io.Gout = G1; io.cdt = 0.5 * dtau; io.wacc = 1.0; io.acc_first = 1;
+    reinit_stage(m, 1, A, io, s);
+    io.Ps = S1; io.Gin = G1; io.Out = S2; io.Gout = G0; io.cdt = 0.5 * dtau; io.wacc = 2.0; io.acc_first = 0;
+    reinit_stage(m, 1, A, io, s);
+    io.Ps = S2; io.Gin = G0; io.Out = S1; io.Gout = G1; io.cdt = dtau;
+    reinit_stage(m, 1, A, io, s);
+    io.Ps = S1; io.Gin = G1; io.Out = psi; io.Gout = G0; io.dt6 = dtau / 6.0;
+    reinit_stage(m, 2, A, io, s);
+  }
+  return hip_check(hipGetLastError(), "kin_reinit launch");
 }
 
 int dg2p_kin_max_dt(dg2p_mesh m, const dg2p_kin_params* kp, const double* u0, double cfl, double* dt, void* work,

@@ -298,4 +298,169 @@ __global__ __launch_bounds__(FIN_THREADS) void k_kin_sum(const double* __restric
   }
 }
 
+// ---- level-set re-initialisation ----------------------------------------------
+// Pseudo-time iteration d psi / d tau = sgn (1 - |grad psi|) + div(nu grad psi)
+// from psi0 = phi - 1/2, sgn = tanh(psi0 / (2 eps |grad psi0|)) (the
+// re-initialisation of the Section "Discontinuous Galerkin discretisation",
+// with the source sign that relaxes |grad psi| towards 1).  The diffusive
+// flux nu grad psi uses the symmetric interior penalty discretisation of the
+// a-fluxes, with KArgs.GammaEps = nu.  Single field psi [E][(p+1)^d].
+
+struct ReinitIO {
+  const double* Ps;  // stage input psi
+  const double* Gin; // nu d_k psi of Ps on the element faces
+  const double* sgn; // smeared sign
+  const double* Pn;  // base of the stage combination (may equal Out)
+  double* Acc;
+  double* Out;
+  double* Gout;
+  double cdt, wacc;
+  int acc_first;
+  double dt6;
+};
+
+template <int DIM>
+__device__ __forceinline__ void reinit_emit(const KArgs& A, double psi, long long e, bool valid, int node,
+                                            const int* ak, const LaneD<DIM>& L, double* G) {
+  constexpr int NFN = (1 << (2 * DIM)) / 4;
+  double g[DIM];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) g[k] = dk<DIM>(psi, k, L, A);
+  if (!valid) return;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    if (ak[k] != 0 && ak[k] != 3) continue;
+    const int side = ak[k] == 3;
+    G[((long long)(2 * k + side) * A.E + e) * NFN + face_index(node, k)] = A.GammaEps * g[k];
+  }
+}
+
+// psi0 = phi - 1/2 -> psi, smeared sign -> sgn, face ingredients of psi0 -> G.
+template <int DIM>
+__global__ __launch_bounds__(BLOCK) void k_reinit_start(KArgs A, const double* __restrict__ phi, double eps_phase,
+                                                        double* __restrict__ psi, double* __restrict__ sgn,
+                                                        double* __restrict__ G) {
+  constexpr int NN = 1 << (2 * DIM);
+  constexpr int EPW = 64 / NN;
+  const long long blk = logical_block(A);
+  if (blk < 0) return;
+  const int lane = threadIdx.x & 63;
+  const long long e0 = (blk * (BLOCK / 64) + (threadIdx.x >> 6)) * EPW + lane / NN;
+  const bool valid = e0 < A.E;
+  const long long e = valid ? e0 : A.E - 1;
+  const int node = lane % NN;
+  int ak[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) ak[k] = (node >> (2 * k)) & 3;
+  LaneD<DIM> L;
+  lane_coeffs<DIM>(A, ak, L);
+  const long long o = e * NN + node;
+  const double p0 = phi[o] - 0.5;
+  double g2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    const double gk = dk<DIM>(p0, k, L, A);
+    g2 = fma(gk, gk, g2);
+  }
+  const double nrm = sqrt(g2 + A.delta * A.delta);
+  if (valid) {
+    psi[o] = p0;
+    sgn[o] = tanh(p0 / (2.0 * eps_phase * nrm));
+  }
+  reinit_emit<DIM>(A, p0, e, valid, node, ak, L, G);
+}
+
+// MODE 1: Acc = (first ? 0 : Acc) + wacc R, Out = Pn + cdt R (+ Gout);
+// MODE 2: Out = Pn + dt6 (Acc + R) (+ Gout).
+template <int DIM, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_reinit_stage(KArgs A, ReinitIO io) {
+  constexpr int NN = 1 << (2 * DIM);
+  constexpr int EPW = 64 / NN;
+  constexpr int NFN = NN / 4;
+  const long long blk = logical_block(A);
+  if (blk < 0) return;
+  const int lane = threadIdx.x & 63;
+  const long long e0 = (blk * (BLOCK / 64) + (threadIdx.x >> 6)) * EPW + lane / NN;
+  const bool valid = e0 < A.E;
+  const long long e = valid ? e0 : A.E - 1;
+  const int node = lane % NN;
+  int ak[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) ak[k] = (node >> (2 * k)) & 3;
+  LaneD<DIM> L;
+  lane_coeffs<DIM>(A, ak, L);
+  const long long o = e * NN + node;
+  const double* __restrict__ Ps = io.Ps;
+  const double psi = Ps[o];
+  double g[DIM];
+  double g2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    g[k] = dk<DIM>(psi, k, L, A);
+    g2 = fma(g[k], g[k], g2);
+  }
+  double R = io.sgn[o] * (1.0 - sqrt(g2));
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) R += dk<DIM>(A.GammaEps * g[k], k, L, A);
+  long long ec[3] = {0, 0, 0};
+  {
+    long long r = e;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      ec[k] = r % A.N[k];
+      r /= A.N[k];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    const int S = 1 << (2 * k);
+    const int akk = ak[k];
+    const bool isface = (akk == 0) || (akk == 3);
+    double symv = 0.0;
+    if (isface) {
+      const int side = akk == 3;
+      const double sm = side ? 1.0 : -1.0;
+      long long c = ec[k] + (side ? 1 : -1);
+      if (c < 0) c = A.N[k] - 1;
+      if (c >= A.N[k]) c = 0;
+      long long estr = 1;
+#pragma unroll
+      for (int kk = 0; kk < k; ++kk) estr *= A.N[kk];
+      const long long en = e + (c - ec[k]) * estr;
+      const double psie = Ps[en * NN + node + (3 - 2 * akk) * S];
+      const double aek = io.Gin[((long long)(2 * k + 1 - side) * A.E + en) * NFN + face_index(node, k)];
+      const double amI = sm * A.GammaEps * g[k], amE = sm * aek;
+      const double jump = psi - psie;
+      const double ahat = 0.5 * (amI + amE) - A.pen[k] * A.GammaEps * jump;
+      R += A.lift[k] * (ahat - amI);
+      symv = sm * A.GammaEps * jump;
+    }
+    const double wlo = sel4(akk, GLL.D[0][0] / GLL.w[0], GLL.D[0][1] / GLL.w[1], GLL.D[0][2] / GLL.w[2],
+                            GLL.D[0][3] / GLL.w[3]) * A.hJ2inv[k];
+    const double whi = sel4(akk, GLL.D[3][0] / GLL.w[0], GLL.D[3][1] / GLL.w[1], GLL.D[3][2] / GLL.w[2],
+                            GLL.D[3][3] / GLL.w[3]) * A.hJ2inv[k];
+    double lo, hi;
+    if (k == 0) {
+      lo = line_end<0>(symv, akk, false);
+      hi = line_end<0>(symv, akk, true);
+    } else if (k == 1) {
+      lo = line_end<1>(symv, akk, false);
+      hi = line_end<1>(symv, akk, true);
+    } else {
+      lo = line_end<2>(symv, akk, false);
+      hi = line_end<2>(symv, akk, true);
+    }
+    R = fma(lo, wlo, fma(hi, whi, R));
+  }
+  double np;
+  if constexpr (MODE == 1) {
+    if (valid) io.Acc[o] = (io.acc_first ? 0.0 : io.Acc[o]) + io.wacc * R;
+    np = io.Pn[o] + io.cdt * R;
+  } else {
+    np = io.Pn[o] + io.dt6 * (io.Acc[o] + R);
+  }
+  if (valid) io.Out[o] = np;
+  reinit_emit<DIM>(A, np, e, valid, node, ak, L, io.Gout);
+}
+
 }  // namespace dg2p

@@ -83,6 +83,7 @@ _SIG = {
     "dg2p_kin_rhs": ([_vp, ctypes.POINTER(KinParams), _dp, _dp, _d, _dp, _vp, _vp], _i),
     "dg2p_kin_rk4": ([_vp, ctypes.POINTER(KinParams), _dp, _dp, _i, _d, _d, _vp, _vp], _i),
     "dg2p_kin_max_dt": ([_vp, ctypes.POINTER(KinParams), _dp, _d, _dp, _vp, _vp], _i),
+    "dg2p_kin_reinit": ([_vp, ctypes.POINTER(KinParams), _dp, _i, _d, _d, _vp, _vp], _i),
     "dg2p_kin_errors": ([_vp, _dp, _dp, _dp, _vp, _vp], _i),
     "dg2p_timing_enable": ([_i], _i),
     "dg2p_timing_read": ([_i, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_longlong)], _i),
@@ -417,3 +418,21 @@ def kin_errors(mesh, phi, phi0, stream=None):
     _check(_lib.dg2p_kin_errors(mesh.handle, _ptr(phi), _ptr(phi0), _ptr(out), ws, _stream(stream)),
            "dg2p_kin_errors")
     return out
+
+
+def kin_reinit(mesh, kp, Phi, n_iter, nu, dtau, stream=None):
+    """Re-initialise Phi[1] (psi) from Phi[0] (phi) in place: n_iter RK4
+    pseudo-time steps of the Eikonal relaxation with viscosity nu."""
+    Phi = _as_kin(mesh, Phi, 2, "Phi")
+    ws = mesh.workspace(None, OP_KIN_RK4, Phi.device)
+    _check(_lib.dg2p_kin_reinit(mesh.handle, ctypes.byref(kp), _ptr(Phi), int(n_iter), float(nu), float(dtau), ws,
+                                _stream(stream)), "dg2p_kin_reinit")
+    return Phi
+
+
+def kin_reinit_params(mesh, cfl=0.1):
+    """(nu_h, dtau): one nodal spacing h / (p+1) and the pseudo step
+    cfl h / (1 + (p+1)^2 d nu_h / h) of unit-speed transport."""
+    h = min((mesh.desc.hi[k] - mesh.desc.lo[k]) / mesh.desc.n_elem[k] for k in range(mesh.dim))
+    nu = h / 4.0
+    return nu, cfl * h / (1.0 + 16.0 * mesh.dim * nu / h)

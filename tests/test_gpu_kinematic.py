@@ -114,25 +114,36 @@ def test_kin_rejects_unsupported():
     assert ei.value.status == dg.EINVAL
 
 
-def test_rider_kothe_full_period_matches_oracle_run():
+@pytest.mark.parametrize("name,ne", [("rk2d", (6, 5)), ("box1", (13,)), ("box3", (2, 3, 2))])
+def test_kin_reinit_parity(name, ne):
+    """Level-set re-initialisation from phi: six RK4 pseudo-time steps."""
+    om, kp, Phi, u0, mesh, lkp = case(name, ne)
+    nu, dtau = K.reinit_params(om)
+    lnu, ldtau = _dg().kin_reinit_params(mesh)
+    assert abs(lnu - nu) <= 1e-15 * nu and abs(ldtau - dtau) <= 1e-15 * dtau
+    psio = K.reinit(Phi[0], om, kp, 6, nu, dtau)
+    P = Phi.cuda().contiguous()
+    _dg().kin_reinit(mesh, lkp, P, 6, nu, dtau)
+    Pc = P.cpu()
+    assert torch.equal(Pc[0], Phi[0])
+    err = float((Pc[1] - psio).abs().max()) / float(psio.abs().max())
+    assert err <= TOL, err
+
+
+@pytest.mark.parametrize("reinit", [False, True])
+def test_rider_kothe_full_period_matches_oracle_run(reinit):
     """One full Rider-Kothe period at 16 x 16 p3 (64^2 DOF, ~11 000 RK4
-    steps) on the GPU against the oracle's stored run of the same problem
-    (tests/golden/rk2d_16x16_p3.json, written by make_kinematic_golden.py)."""
-    path = os.path.join(HERE, "golden", "rk2d_16x16_p3.json")
+    steps; with re-initialisation of psi every 2000 steps) on the GPU against
+    the oracle's stored run of the same problem (tests/golden/, written by
+    make_kinematic_golden.py)."""
+    name = "rk2d_16x16_p3_reinit.json" if reinit else "rk2d_16x16_p3.json"
+    path = os.path.join(HERE, "golden", name)
     if not os.path.exists(path):
         pytest.skip("oracle golden run not generated")
     gold = json.load(open(path))
-    om, kp, Phi, u0, mesh, lkp = case("rk2d", (16, 16))
-    dg = _dg()
-    u0d = u0.cuda()
-    dt0 = float(dg.kin_max_dt(mesh, lkp, u0d, cfl=0.1).cpu())
-    ns = int(math.ceil(4.0 / dt0))
-    assert ns == gold["steps"]
-    P = Phi.cuda().contiguous()
-    P0 = P[0].clone()
-    dg.kin_rk4(mesh, lkp, P, u0d, ns, 0.0, 4.0 / ns)
-    e = dg.kin_errors(mesh, P[0].contiguous(), P0).cpu().tolist()
-    l1, em = e[0], e[1] / e[2]
-    print("L1", l1, gold["l1"], "E_m", em, gold["mass_error"])
-    assert abs(l1 - gold["l1"]) <= 1e-9 * gold["l1"]
-    assert abs(em - gold["mass_error"]) <= 1e-6 * abs(gold["mass_error"]) + 1e-13
+    from paper_2306_05002_amd import kinematic
+    r = kinematic.rider_kothe(16, reinit_every=2000 if reinit else 0)
+    assert r["steps"] == gold["steps"]
+    print("L1", r["l1"], gold["l1"], "E_m", r["mass_error"], gold["mass_error"])
+    assert abs(r["l1"] - gold["l1"]) <= 1e-9 * gold["l1"]
+    assert abs(r["mass_error"] - gold["mass_error"]) <= 1e-6 * abs(gold["mass_error"]) + 1e-13

@@ -215,3 +215,63 @@ def test_profile_advection_converges_at_p_plus_1():
             errs.append(K.l1_error(Phi[0], fields(T)[0], mesh))
         orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
         assert orders[-1] > 3.7, (G, errs, orders)
+
+
+# ---- level-set re-initialisation ------------------------------------------------
+def test_reinit_diffusion_block_symmetric_nsd():
+    """sgn = 0: the re-initialisation operator is the SIPG Laplacian with the
+    vanishing viscosity nu_h; W A is symmetric, negative semidefinite with the
+    constants as its only null space, and conservative."""
+    mesh = _mesh(2, 3)
+    nu, _ = K.reinit_params(mesh)
+    sgn = torch.zeros(mesh.E, mesh.nn)
+
+    def r(v):
+        return K.reinit_rhs(v.reshape(mesh.E, mesh.nn), sgn, mesh, nu, 1.0).reshape(-1)
+
+    x0 = torch.rand(mesh.E * mesh.nn)
+    Jm = torch.autograd.functional.jacobian(r, x0)
+    W = mesh.node_weights().repeat(mesh.E)
+    A = W[:, None] * Jm
+    scale = float(torch.abs(A).max())
+    assert float(torch.abs(A - A.T).max()) < 1e-10 * scale
+    ev = torch.linalg.eigvalsh(0.5 * (A + A.T))
+    assert float(ev.max()) < 1e-9 * scale
+    assert int((torch.abs(ev) < 1e-9 * scale).sum()) == 1
+    assert abs(float((W * r(x0)).sum())) < 1e-11 * scale
+
+
+def test_reinit_source_relaxes_slope():
+    """psi = 2 (x - 1/2), sgn = sign(psi): away from the periodic seam the
+    diffusion of a linear field vanishes and R = sgn (1 - |grad psi|) = -sgn,
+    i.e. the iteration lowers |psi| where the slope exceeds 1 (the standard
+    Eikonal relaxation; fails on a flipped source sign)."""
+    mesh = _mesh(1, 8)
+    X = mesh.node_coords()[0]
+    psi = 2.0 * (X - 0.5)
+    sgn = torch.sign(psi)
+    nu, _ = K.reinit_params(mesh)
+    R = K.reinit_rhs(psi, sgn, mesh, nu, 1.0)
+    inner = slice(1, 7)  # elements not touching the seam at x = 0 = 1
+    assert float(torch.abs(R[inner] + sgn[inner]).max()) < 1e-12
+
+
+def test_reinit_converges_to_distance_near_interface():
+    """Slab phi = sigmoid((|x - 1/2| - 1/4) / eps): the iteration from
+    psi0 = phi - 1/2 keeps the zero level at x = 1/4, 3/4 and turns the
+    slope there into 1 (a signed distance near the interface)."""
+    N = 32
+    mesh = _mesh(1, N)
+    X = mesh.node_coords()[0]
+    eps = 0.5 / N
+    kp = K.KinParams(eps=eps)
+    phi = torch.sigmoid((torch.abs(X - 0.5) - 0.25) / eps)
+    nu, dtau = K.reinit_params(mesh)
+    psi = K.reinit(phi, mesh, kp, 800, nu, dtau)
+    g = K._dk(psi.reshape(N, 4), 0, mesh).reshape(-1)
+    xs, ps = X.reshape(-1), psi.reshape(-1)
+    near = (torch.abs(xs - 0.25) < 0.02) | (torch.abs(xs - 0.75) < 0.02)
+    assert float(torch.abs(g[near].abs() - 1.0).max()) < 1e-3
+    for x0 in (0.25, 0.75):
+        i = int(torch.argmin(torch.abs(xs - x0)))
+        assert abs(float(ps[i])) < 1e-6
