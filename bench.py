@@ -40,6 +40,7 @@ WORKLOAD_DESC = {
     "shock2d": "2D shock onto water cylinder, 512x256 quads, p=3, FP64",
     "rt3d": "3D heavy-over-light box, 96^3 hexahedra, p=3, viscous + CSF + gravity, FP64",
     "adjoint2d": "2D droplet 128x128 p=3, viscous + CSF, FP64 forward",
+    "waterair2d": "2D water droplet in air (density ratio 1000, P_inf 6000), 24x24 quads, p=3, FP64",
 }
 
 
@@ -138,6 +139,47 @@ def kinematic_section():
                      "value": 4.0 * r0["dof"] * r0["steps"] / (r0["ms"] * 1e-3)})
     return {"workload": "rk2d: Rider-Kothe vortex, [0,1]^2 periodic, p=3, eps=h/2, Gamma=1, T=4, RK4, CFL 0.1",
             "unit": "DOF-updates/s", "runs": rows}
+
+
+def waterair_section():
+    """The paper's water droplet in air (24 x 24, p = 3, density ratio 1000,
+    P_inf 6000, u = (5, 5)) for five advection periods with a fixed step, in
+    FP64 and the two mixed forms: interface equilibrium (max |P - 1|,
+    max |u - (5, 5)|), the droplet's shape (L1 of alpha against the initial
+    field, which it should return to) and throughput."""
+    import torch
+    from paper_2306_05002_amd import dg2p, workloads
+    cfg = workloads.config("waterair2d")
+    P64 = dg2p.make_params(cfg["params"])
+    mesh = dg2p.mesh_from_config(cfg, P64)
+    U0 = dg2p.prim_to_cons(mesh, P64, dg2p.prim_tensor(
+        workloads.primitive_fields(cfg, mesh.node_coords()), cfg["dim"]))
+    dt0 = float(dg2p.max_dt(mesh, P64, U0, cfl=0.1).cpu())
+    ns = int(math.ceil(cfg["t_end"] / dt0))
+    dtf = torch.tensor([cfg["t_end"] / ns], dtype=torch.float64, device="cuda")
+    a0 = U0[3 + cfg["dim"]].contiguous()
+    dof = mesh.E * mesh.nn * mesh.nf
+    runs = {}
+    for prec in ("fp64", "fp32", "bf16"):
+        Pm = dg2p.make_params(cfg["params"], precision=prec)
+        U = U0.clone()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        dg2p.advance(mesh, Pm, U, ns, dt_fixed=dtf)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        m = dg2p.monitors(mesh, P64, U, p_ref=1.0, u_ref=[5.0, 5.0])
+        e = dg2p.kin_errors(mesh, U[3 + cfg["dim"]].contiguous(), a0).cpu().tolist()
+        runs[prec] = {"dev_p": m["dev_p"], "dev_u": m["dev_u"], "nonphys": m["nonphys"],
+                      "alpha_range": [m["min_alpha"], m["max_alpha"]],
+                      "alpha_l1_vs_initial": e[0], "alpha_mass_error": e[1] / e[2],
+                      "ms_per_step": ms / ns, "value": 3.0 * dof * ns / (ms * 1e-3)}
+    return {"workload": "waterair2d: water droplet R=25/89 in air, 24x24 p=3, rho 1e-3/1, P_inf 0/6000, "
+                        "u=(5,5), eps=h/2, Gamma=5, five periods (t=1), fixed dt",
+            "steps": ns, "unit": "DOF-updates/s", "runs": runs}
 
 
 # steps after which the mixed-precision forms' field errors are stated
@@ -333,8 +375,10 @@ def main():
                    "dL_dsigma": gs}
 
     kinematic = None
+    waterair = None
     if not args.no_variants:
         kinematic = kinematic_section()
+        waterair = waterair_section()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -383,6 +427,7 @@ def main():
         "mixed_precision": variants,
         "adjoint": adjoint,
         "kinematic": kinematic,
+        "water_air_droplet": waterair,
         "cpu_baseline": cpu,
         "monitors": {"nonphys": mon["nonphys"], "min_alpha": mon["min_alpha"],
                      "max_alpha": mon["max_alpha"]},

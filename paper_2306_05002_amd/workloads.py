@@ -18,6 +18,9 @@ Configurations (all p = 3, i.e. four GLL nodes per direction):
   rt3d       3D heavy-over-light box, 96^3, gravity, viscosity, surface tension,
              slip walls in z
   adjoint2d  drop2d plus viscosity 1e-3 and surface tension 1e-2
+  waterair2d the paper's water droplet (R 25/89) in air, 24 x 24, density
+             ratio 1000 (rho 1e-3 / 1), P_inf 0 / 6000, u = (5, 5), P = 1,
+             Gamma 5, five advection periods (t = 1)
 Phase 1 is air (gamma 1.4, P_inf 0), phase 2 water-like (gamma 4.4,
 P_inf 0.6); alpha is the volume fraction of phase 1 and psi increases
 towards phase 1, alpha = 1 / (1 + exp(-psi / eps)).
@@ -28,13 +31,14 @@ import math
 import numpy as np
 
 ORDER = 3
-NAMES = ("drop1d", "drop2d", "shock2d", "rt3d", "adjoint2d")
+NAMES = ("drop1d", "drop2d", "shock2d", "rt3d", "adjoint2d", "waterair2d")
 FULL_ELEMS = {
     "drop1d": (100,),
     "drop2d": (128, 128),
     "shock2d": (512, 256),
     "rt3d": (96, 96, 96),
     "adjoint2d": (128, 128),
+    "waterair2d": (24, 24),
 }
 
 
@@ -67,7 +71,8 @@ def config(name, n_elem=None):
     """Mesh description and physical parameters of a configuration.
 
     ``n_elem`` overrides the element counts (reduced sizes for parity tests);
-    eps follows the rule eps = h / (2 (p+1)) of the configuration's own grid.
+    eps follows the rule eps = h / (2 (p+1)) of the configuration's own grid
+    (waterair2d: eps = h / 2).
     """
     if name not in NAMES:
         raise KeyError(name)
@@ -94,6 +99,13 @@ def config(name, n_elem=None):
         cfg["bc_prim"] = {(0, 0): dict(alpha=1.0, psi=0.0, rho1=rho_post,
                                        rho2=base["rho0"][1], u=(u_post, 0.0),
                                        P=p_post)}
+    elif name == "waterair2d":
+        # the paper's water droplet in air: density ratio 1000, P_inf of
+        # water 6000, u = (5, 5), five advection periods
+        cfg.update(dim=2, lo=(0.0, 0.0), hi=(1.0, 1.0),
+                   bc=[("periodic", "periodic")] * 2, t_end=1.0)
+        base.update(rho0=(1e-3, 1.0), pinf=(0.0, 6.0e3), Gamma=5.0)
+        cfg.update(steps=200)
     elif name == "rt3d":
         cfg.update(dim=3, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
                    bc=[("periodic", "periodic")] * 2 + [("slip_wall", "slip_wall")],
@@ -103,7 +115,9 @@ def config(name, n_elem=None):
     if len(n_elem) != d:
         raise ValueError("n_elem has the wrong length")
     h = min((cfg["hi"][k] - cfg["lo"][k]) / n_elem[k] for k in range(d))
-    base["eps"] = 0.5 * h / (p + 1)
+    # eps: half a nodal spacing; the water droplet in air (air density 1e-3,
+    # where an overshoot of alpha by 1e-3 empties the air) two nodal spacings
+    base["eps"] = (0.5 * h) if name == "waterair2d" else 0.5 * h / (p + 1)
     cfg["params"] = base
     cfg.setdefault("bc_prim", {})
     return cfg
@@ -166,6 +180,10 @@ def primitive_fields(cfg, coords, variant=None):
         psi = np.sqrt((X[0] - 0.5) ** 2 + (X[1] - 0.5) ** 2) - 0.15
         u[0] = 1.0
         u[1] = 0.5
+    elif name == "waterair2d":
+        psi = np.sqrt((X[0] - 0.5) ** 2 + (X[1] - 0.5) ** 2) - 25.0 / 89.0
+        u[0] = 5.0
+        u[1] = 5.0
     elif name == "shock2d":
         psi = np.sqrt((X[0] - 0.5) ** 2 + (X[1] - 0.5) ** 2) - 0.1
         h = (cfg["hi"][0] - cfg["lo"][0]) / cfg["n_elem"][0]

@@ -64,6 +64,7 @@ SMALL = [
     ("adjoint2d", (10, 9), None),      # viscous + CSF
     ("rt3d", (5, 4, 6), None),         # viscous + CSF + gravity + slip walls
     ("rt3d", (1, 1, 2), None),
+    ("waterair2d", (6, 5), None),      # density ratio 1000, P_inf 6000
 ]
 
 
@@ -168,6 +169,27 @@ def test_determinism_bitwise():
     dg.rk_step(mesh, P, A, dt)
     dg.rk_step(mesh, P, B, dt)
     assert torch.equal(A, B)
+
+
+def test_water_air_interface_equilibrium():
+    """The paper's water droplet in air (density ratio 1000, stiffened water
+    with P_inf = 6000, u = (5, 5)): 400 FP64 steps keep P and u uniform to the
+    round-off floor of P = (rho e - Pi)/xi (Pi ~ 8e3), the state physical, and
+    match the oracle after 20 steps."""
+    cfg, om, prm, U0, mesh, P = gpu_case("waterair2d", (12, 12))
+    dg = _dg()
+    U = U0.cuda().contiguous()
+    dt = dg.max_dt(mesh, P, U)
+    Uo = U0
+    for _ in range(20):
+        Uo = oracle.rk_step(Uo, float(dt.cpu()), om, prm)
+    dg.advance(mesh, P, U, 20, dt_fixed=dt)
+    assert max(state_errors(U.cpu(), Uo, prm, om.d)) <= 1e-11
+    dg.advance(mesh, P, U, 380, dt_fixed=dt)
+    m = dg.monitors(mesh, P, U, p_ref=1.0, u_ref=[5.0, 5.0])
+    print("water-air after 400 steps", m["dev_p"], m["dev_u"], m["min_alpha"], m["max_alpha"])
+    assert m["nonphys"] == 0
+    assert m["dev_p"] < 1e-7 and m["dev_u"] < 1e-7
 
 
 def test_interface_equilibrium_on_gpu():

@@ -129,21 +129,26 @@ def test_conservation_periodic(name, ne, variant):
         assert abs(float((R[d + 3] * W).sum())) > 1e-12 * scale[d + 3]
 
 
-@pytest.mark.parametrize("name,ne", [("drop1d", None), ("drop2d", (12, 10))])
+@pytest.mark.parametrize("name,ne", [("drop1d", None), ("drop2d", (12, 10)), ("waterair2d", (8, 8))])
 def test_interface_equilibrium(name, ne):
     """Uniform u and P across the interface with phase densities equal to
     rho_l^(0): R_rhou = u R_rho and dP/dt = 0 to round-off (the interface
     equilibrium condition the quasi-conservative form is built for), and P, u
-    stay uniform over 30 SSP-RK3 steps."""
+    stay uniform over 30 SSP-RK3 steps.  The water droplet in air (density
+    ratio 1000, P_inf 6000) takes P from rho e - Pi with Pi ~ 8e3, so its
+    round-off floor is that of Pi / xi ~ 3e4 times larger."""
     cfg, mesh, prm, U0 = oracle_setup(name, n_elem=ne)
     d = mesh.d
     R = oracle.rhs(U0, mesh, prm)
     pr = oracle.primitives(U0, d, prm)
     u = pr["u"]
+    # P = (rho e - Pi) / xi: its round-off is that of Pi / xi (stiffened water)
+    g2, p2 = prm.gamma[1], prm.pinf[1]
+    cancel = max(1.0, (g2 * p2 / (g2 - 1)) * (g2 - 1))
     Rrho = R[0] + R[1]
     scale = float(torch.abs(R[0]).max() + torch.abs(R[1]).max())
     for j in range(d):
-        assert float(torch.abs(R[2 + j] - u[j] * Rrho).max()) < 1e-13 * scale * 10
+        assert float(torch.abs(R[2 + j] - u[j] * Rrho).max()) < 1e-12 * scale * cancel
     # linearised pressure rate: xi dP = dE - u.d(rho u) + k d rho - (xi' P + Pi') d alpha
     g1, g2 = prm.gamma
     p1, p2 = prm.pinf
@@ -151,13 +156,15 @@ def test_interface_equilibrium(name, ne):
     dpi = g1 * p1 / (g1 - 1) - g2 * p2 / (g2 - 1)
     dP = (R[2 + d] - sum(u[j] * R[2 + j] for j in range(d)) + pr["kin"] * Rrho
           - (dxi * pr["P"] + dpi) * R[3 + d]) / pr["xi"]
-    assert float(torch.abs(dP).max()) < 1e-12 * float(torch.abs(R[2 + d]).max())
+    assert float(torch.abs(dP).max()) < 1e-12 * float(torch.abs(R[2 + d]).max()) * cancel
+    floor = 1e-12 * cancel
     dt = oracle.max_dt(U0, mesh, prm)
     U = U0
     for _ in range(30):
         U = oracle.rk_step(U, dt, mesh, prm)
-    m = oracle.monitors(U, mesh, prm, p_ref=1.0, u_ref=cfg and [1.0, 0.5][:d])
-    assert m["dev_p"] < 1e-12 and m["dev_u"] < 1e-12
+    u_ref = [float(u[j].flatten()[0]) for j in range(d)]
+    m = oracle.monitors(U, mesh, prm, p_ref=1.0, u_ref=u_ref)
+    assert m["dev_p"] < floor and m["dev_u"] < floor, (m["dev_p"], m["dev_u"], floor)
 
 
 @pytest.mark.parametrize("bc", ["periodic", "slip_wall", "dirichlet", "extrapolate"])
