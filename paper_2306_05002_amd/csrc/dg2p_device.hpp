@@ -48,10 +48,10 @@ constexpr int BLOCK = 256;      // threads per workgroup (4 independent waves)
 #ifndef DG2P_WAVES_3D
 #define DG2P_WAVES_3D 1
 #endif
-// issue the face-neighbour loads at kernel entry (hides their latency behind
-// the volume terms at the cost of registers); used where waves are few
-#ifndef DG2P_PREFETCH_MAXDIM
-#define DG2P_PREFETCH_MAXDIM 0
+// Ends a value's code motion at this point (an empty asm statement that
+// takes and returns the value in a vector register).
+#ifndef DG2P_PIN
+#define DG2P_PIN(x) asm volatile("" : "+v"(x))
 #endif
 template <int DIM>
 constexpr int min_waves() {
@@ -726,6 +726,168 @@ __global__ __launch_bounds__(BLOCK) void k_ingredients(KArgs A, const double* __
   emit<DIM, VISC, true, 1, PR>(A, q, e, valid, node, ak, L, G, rec, blk);
 }
 
+// ---- face fluxes ------------------------------------------------------------------
+template <int DIM>
+__device__ __forceinline__ double pick(const double* v, int k) {
+  if constexpr (DIM == 1) {
+    return v[0];
+  } else if constexpr (DIM == 2) {
+    return k ? v[1] : v[0];
+  } else {
+    return k == 0 ? v[0] : (k == 1 ? v[1] : v[2]);
+  }
+}
+
+// Convective flux of conservative equation qi along axis kd (velocity
+// component uk = u_kd).
+template <int DIM>
+__device__ __forceinline__ double conv_flux_k(const double* q, const Prim& p, int qi, int kd, double uk) {
+  if (qi < 2) return q[qi] * uk;
+  if (qi < 2 + DIM) return q[qi] * uk + ((qi - 2) == kd ? p.P : 0.0);
+  return (q[2 + DIM] + p.P) * uk;
+}
+
+// Contributions of one face node of an element to that node: Rc[f] (lift
+// factor included) for every field, and the SIPG symmetric-term values symv
+// (conservative equations, then alpha) to be spread along the normal line.
+// Face normal axis kd, side 0 (low) / 1 (high).  The element's own trace:
+// q, p, a.e_kd (a_k), the viscous traction mu S[j][kd] (mu, Sk) and, for
+// Dirichlet ghosts, d_kd alpha and n_kd (gA_k, nh_k).  The neighbour's trace
+// is read from Us (element en, node nodee) with its ingredients from Gin
+// (face node fn), or built as the boundary ghost when bnd.
+template <int DIM, bool VISC, bool DIRI>
+__device__ __forceinline__ void face_flux(const KArgs& A, const double* __restrict__ Us,
+                                          const double* __restrict__ Gin, int kd, int side, bool bnd, long long en,
+                                          int nodee, int fn, const double* q, const Prim& pr, double a_k, double mu,
+                                          const double* Sk, double gA_k, double nh_k, double* Rc, double* symv) {
+  constexpr int NN = 1 << (2 * DIM);
+  constexpr int NF = DIM + 5;
+  constexpr int NC = DIM + 3;
+  constexpr int C = VISC ? 1 + DIM : 1;
+  constexpr int NFN = NN / 4;
+  const double sm = side ? 1.0 : -1.0;
+  double qe[NF];
+  double aek;
+  double tek[DIM];
+  if (!bnd) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) qe[f] = Us[(f * A.E + en) * NN + nodee];
+    const long long gb = (long long)((2 * kd + 1 - side) * C) * A.E;
+    aek = Gin[(gb + en) * NFN + fn];
+    if constexpr (VISC) {
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) tek[j] = Gin[(gb + (long long)(1 + j) * A.E + en) * NFN + fn];
+    }
+  } else {
+    const int kind = A.bc[kd][side];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) qe[f] = q[f];
+    aek = a_k;
+    if constexpr (VISC) {
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) tek[j] = mu * Sk[j];
+    }
+    if (kind == DG2P_BC_SLIP_WALL) {
+#pragma unroll
+      for (int j = 0; j < DIM; ++j)
+        if (j == kd) qe[2 + j] = -q[2 + j];
+      aek = -a_k;
+      if constexpr (VISC) {
+#pragma unroll
+        for (int j = 0; j < DIM; ++j)
+          if (j != kd) tek[j] = -tek[j];
+      }
+    }
+    if constexpr (DIRI) {
+      if (kind == DG2P_BC_DIRICHLET) {
+#pragma unroll
+        for (int f = 0; f < 4 + DIM; ++f) qe[f] = A.bcs[kd][side][f];
+        const double ag = qe[3 + DIM];
+        aek = A.Gamma * (A.eps * gA_k - (ag * (1.0 - ag)) * nh_k);
+        if constexpr (VISC) {
+          const double mug = A.mu1 * ag + A.mu2 * (1.0 - ag);
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) tek[j] = mug * Sk[j];
+        }
+      }
+    }
+  }
+  Prim pe;
+  closure<DIM>(A, qe, pe);
+  const double uIk = pick<DIM>(pr.u, kd), uEk = pick<DIM>(pe.u, kd);
+  const double umI = sm * uIk, umE = sm * uEk;
+  const double lam = fmax(fabs(umI) + pr.c, fabs(umE) + pe.c);
+  const double amI = sm * a_k, amE = sm * aek;
+  const double alI = q[3 + DIM], alE = qe[3 + DIM];
+  const double jump = alI - alE;
+  const double penk = pick<DIM>(A.pen, kd);
+  const double ahat = 0.5 * (amI + amE) - penk * A.GammaEps * jump;
+  const double Lf = pick<DIM>(A.lift, kd);
+  double etav = 0.0;
+  if constexpr (VISC) {
+    const double mue = A.mu1 * alE + A.mu2 * (1.0 - alE);
+    etav = penk * (0.5 * (mu + mue));
+  }
+#pragma unroll
+  for (int qi = 0; qi < NC; ++qi) {
+    const double FmI = sm * conv_flux_k<DIM>(q, pr, qi, kd, uIk);
+    const double FmE = sm * conv_flux_k<DIM>(qe, pe, qi, kd, uEk);
+    const double Fhat = 0.5 * (FmI + FmE) - 0.5 * lam * (qe[qi] - q[qi]);
+    const double sI = s_coef<DIM>(A, pr, qi), sE = s_coef<DIM>(A, pe, qi);
+    const double sbar = 0.5 * (sI + sE);
+    double t = (FmI - Fhat) + (sbar * ahat - sI * amI);
+    if constexpr (VISC) {
+      if (qi >= 2) {
+        double VmI, VmE, pen;
+        if (qi < 2 + DIM) {
+          const int j = qi - 2;
+          VmI = sm * (mu * Sk[j]);
+          VmE = sm * tek[j];
+          pen = etav * (pr.u[j] - pe.u[j]);
+        } else {
+          double tuI = 0.0, tuE = 0.0, du = 0.0;
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) {
+            tuI += (mu * Sk[j]) * pr.u[j];
+            tuE += tek[j] * pe.u[j];
+            du += (pr.u[j] - pe.u[j]) * (0.5 * (pr.u[j] + pe.u[j]));
+          }
+          VmI = sm * tuI;
+          VmE = sm * tuE;
+          pen = etav * du;
+        }
+        const double Vhat = 0.5 * (VmI + VmE) - pen;
+        t += Vhat - VmI;
+      }
+    }
+    Rc[qi] = Lf * t;
+    symv[qi] = sm * sbar * A.GammaEps * jump;
+  }
+  const double KA = 0.5 * (lam - umI) * (alE - alI);
+  Rc[3 + DIM] = Lf * (KA + (ahat - amI));
+  symv[NC] = sm * A.GammaEps * jump;
+  Rc[4 + DIM] = Lf * (0.5 * (lam - umI) * (qe[4 + DIM] - q[4 + DIM]));
+}
+
+// SIPG symmetric term: the values symv of the face nodes at the two ends of
+// each line along K, weighted with D[end][a] / (2 w_a J_K^2) (end = 0 for the
+// low face, 3 for the high face), added to every node a of the line.
+template <int K, int DIM>
+__device__ __forceinline__ void spread_sym(const KArgs& A, int akk, const double* symv, double* R) {
+  constexpr int NC = DIM + 3;
+  const double wlo = sel4(akk, GLL.D[0][0] / GLL.w[0], GLL.D[0][1] / GLL.w[1], GLL.D[0][2] / GLL.w[2],
+                          GLL.D[0][3] / GLL.w[3]) * A.hJ2inv[K];
+  const double whi = sel4(akk, GLL.D[3][0] / GLL.w[0], GLL.D[3][1] / GLL.w[1], GLL.D[3][2] / GLL.w[2],
+                          GLL.D[3][3] / GLL.w[3]) * A.hJ2inv[K];
+#pragma unroll
+  for (int i = 0; i <= NC; ++i) {
+    const double lo = line_end<K>(symv[i], akk, false);
+    const double hi = line_end<K>(symv[i], akk, true);
+    const int f = (i < NC) ? i : 3 + DIM;
+    R[f] = fma(lo, wlo, fma(hi, whi, R[f]));
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Stage pass: residual of each element (volume terms, sources, all faces, SIPG
 // symmetric term), then MODE 0: store R; MODE 1: U_out = U_s + dt R;
@@ -737,8 +899,6 @@ __global__ __launch_bounds__(BLOCK, min_waves<DIM>()) void k_stage(KArgs A, Stag
   constexpr int EPW = 64 / NN;
   constexpr int NF = DIM + 5;
   constexpr int NC = DIM + 3;  // conservative equations
-  constexpr int C = VISC ? 1 + DIM : 1;
-  constexpr int NFN = NN / 4;
   const long long blk = logical_block(A);
   if (blk < 0) return;
   const int lane = threadIdx.x & 63;
@@ -766,7 +926,6 @@ __global__ __launch_bounds__(BLOCK, min_waves<DIM>()) void k_stage(KArgs A, Stag
       r /= A.N[k];
     }
   }
-  constexpr bool PF = DIM <= DG2P_PREFETCH_MAXDIM;
   long long enb[DIM];
   bool bndk[DIM];
 #pragma unroll
@@ -787,23 +946,6 @@ __global__ __launch_bounds__(BLOCK, min_waves<DIM>()) void k_stage(KArgs A, Stag
     for (int kk = 0; kk < k; ++kk) estr *= A.N[kk];
     enb[k] = (isface && !bnd) ? e + (c - ec[k]) * estr : e;
     bndk[k] = bnd;
-  }
-  double qpf[PF ? DIM : 1][NF];
-  double apf[PF ? DIM : 1][C];
-  if constexpr (PF) {
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      const int akk = ak[k];
-      const bool isface = (akk == 0) || (akk == 3);
-      const int nodee = isface ? node + (3 - 2 * akk) * (1 << (2 * k)) : node;
-#pragma unroll
-      for (int f = 0; f < NF; ++f) qpf[k][f] = Us[(f * A.E + enb[k]) * NN + nodee];
-      const int side = akk == 3;
-      const int fn = face_index(node, k);
-      const long long gb = (long long)((2 * k + 1 - side) * C) * A.E;
-#pragma unroll
-      for (int cc = 0; cc < C; ++cc) apf[k][cc] = io.Gin[(gb + (long long)cc * A.E + enb[k]) * NFN + fn];
-    }
   }
   double dt_fused = 0.0;
   if constexpr (MODE == 1) {
@@ -884,152 +1026,124 @@ __global__ __launch_bounds__(BLOCK, min_waves<DIM>()) void k_stage(KArgs A, Stag
     }
   }
 
+  // Pin the volume and source sums here: otherwise their multiply-adds are
+  // sunk past the face code while the lane rotations feeding them stay
+  // behind, and the rotated values are spilled.
+#pragma unroll
+  for (int f = 0; f < NF; ++f) DG2P_PIN(R[f]);
+
   // faces
   const double* __restrict__ Gin = io.Gin;
+  if constexpr (DIM == 2) {
+    // The 16 face nodes of a quad (4 faces x 4 nodes) are spread over its 16
+    // lanes, one face evaluation each: a lane with a_x in {0, 3} evaluates the
+    // x-face at its own node; a lane with a_x = 1 (2) evaluates the low (high)
+    // y-face at node (a_y, 0) ((a_y, 3)).  The owner node's trace comes from
+    // its lane and the results go back to it by lane exchanges, so no face is
+    // evaluated on half-idle lanes.
+    const bool xjob = (ak[0] == 0) || (ak[0] == 3);
+    const int jside = xjob ? (ak[0] == 3) : (ak[0] == 2);
+    const int onode = xjob ? node : ak[1] + (jside ? 12 : 0);
+    const int olane = (lane & 48) | onode;
+    double qo[NF];
 #pragma unroll
-  for (int k = 0; k < DIM; ++k) {
-    const int S = 1 << (2 * k);
-    const int akk = ak[k];
-    const bool isface = (akk == 0) || (akk == 3);
+    for (int f = 0; f < NF; ++f) qo[f] = __shfl(q[f], olane);
+    Prim po;
+    po.rho = __shfl(pr.rho, olane);
+    po.u[0] = __shfl(pr.u[0], olane);
+    po.u[1] = __shfl(pr.u[1], olane);
+    po.u[2] = 0.0;
+    po.kin = __shfl(pr.kin, olane);
+    po.P = __shfl(pr.P, olane);
+    po.c = __shfl(pr.c, olane);
+    po.sE = __shfl(pr.sE, olane);
+    const double a1 = __shfl(g.a[1], olane);
+    const double ao = xjob ? g.a[0] : a1;
+    double mu = 0.0, Sk[2] = {0.0, 0.0};
+    if constexpr (VISC) {
+      const double mu1 = __shfl(g.mu, olane), s01 = __shfl(g.S[0][1], olane), s11 = __shfl(g.S[1][1], olane);
+      mu = xjob ? g.mu : mu1;
+      Sk[0] = xjob ? g.S[0][0] : s01;
+      Sk[1] = xjob ? g.S[1][0] : s11;
+    }
+    double gAk = 0.0, nhk = 0.0;
+    if constexpr (DIRI) {
+      const double ga1 = __shfl(g.gA[1], olane), nh1 = __shfl(g.nh[1], olane);
+      gAk = xjob ? g.gA[0] : ga1;
+      nhk = xjob ? g.nh[0] : nh1;
+    }
+    // neighbour across the job's face
+    long long en;
+    bool bnd;
+    if (xjob) {
+      en = enb[0];
+      bnd = bndk[0];
+    } else {
+      long long c = ec[1] + (jside ? 1 : -1);
+      bnd = false;
+      if (c < 0 || c >= A.N[1]) {
+        if ((jside ? A.bc[1][1] : A.bc[1][0]) == DG2P_BC_PERIODIC)
+          c = (c < 0) ? A.N[1] - 1 : 0;
+        else
+          bnd = true;
+      }
+      en = bnd ? e : e + (c - ec[1]) * A.N[0];
+    }
+    const int nodee = xjob ? node + (3 - 2 * ak[0]) : onode + (jside ? -12 : 12);
+    const int fn = xjob ? (node >> 2) : ak[1];
+    double Rc[NF], sv[NC + 1];
+    face_flux<2, VISC, DIRI>(A, Us, Gin, xjob ? 0 : 1, jside, bnd, en, nodee, fn, qo, po, ao, mu, Sk, gAk, nhk,
+                             Rc, sv);
     double symv[NC + 1];
 #pragma unroll
-    for (int i = 0; i <= NC; ++i) symv[i] = 0.0;
-    if (isface) {
-      const int side = akk == 3;
-      const double sm = side ? 1.0 : -1.0;
-      const bool bnd = bndk[k];
-      double qe[NF];
-      double aek;
-      double tek[DIM];
-      if (!bnd) {
-        if constexpr (PF) {
+    for (int i = 0; i <= NC; ++i) symv[i] = xjob ? sv[i] : 0.0;
+    if (xjob) {
 #pragma unroll
-          for (int f = 0; f < NF; ++f) qe[f] = qpf[k][f];
-          aek = apf[k][0];
-          if constexpr (VISC) {
-#pragma unroll
-            for (int j = 0; j < DIM; ++j) tek[j] = apf[k][(1 + j) < C ? 1 + j : 0];
-          }
-        } else {
-          const long long en = enb[k];
-          const int nodee = node + (3 - 2 * akk) * S;
-#pragma unroll
-          for (int f = 0; f < NF; ++f) qe[f] = Us[(f * A.E + en) * NN + nodee];
-          const int fn = face_index(node, k);
-          const long long gb = (long long)((2 * k + 1 - side) * C) * A.E;
-          aek = Gin[(gb + en) * NFN + fn];
-          if constexpr (VISC) {
-#pragma unroll
-            for (int j = 0; j < DIM; ++j) tek[j] = Gin[(gb + (long long)(1 + j) * A.E + en) * NFN + fn];
-          }
-        }
-      } else {
-        const int kind = A.bc[k][side];
-#pragma unroll
-        for (int f = 0; f < NF; ++f) qe[f] = q[f];
-        aek = g.a[k];
-        if constexpr (VISC) {
-#pragma unroll
-          for (int j = 0; j < DIM; ++j) tek[j] = g.mu * g.S[j][k];
-        }
-        if (kind == DG2P_BC_SLIP_WALL) {
-          qe[2 + k] = -q[2 + k];
-          aek = -g.a[k];
-          if constexpr (VISC) {
-#pragma unroll
-            for (int j = 0; j < DIM; ++j)
-              if (j != k) tek[j] = -tek[j];
-          }
-        }
-        if constexpr (DIRI) {
-          if (kind == DG2P_BC_DIRICHLET) {
-#pragma unroll
-            for (int f = 0; f < 4 + DIM; ++f) qe[f] = A.bcs[k][side][f];
-            const double ag = qe[3 + DIM];
-            aek = A.Gamma * (A.eps * g.gA[k] - (ag * (1.0 - ag)) * g.nh[k]);
-            if constexpr (VISC) {
-              const double mug = A.mu1 * ag + A.mu2 * (1.0 - ag);
-#pragma unroll
-              for (int j = 0; j < DIM; ++j) tek[j] = mug * g.S[j][k];
-            }
-          }
-        }
-      }
-      Prim pe;
-      closure<DIM>(A, qe, pe);
-      const double umI = sm * pr.u[k], umE = sm * pe.u[k];
-      const double lam = fmax(fabs(umI) + pr.c, fabs(umE) + pe.c);
-      const double amI = sm * g.a[k], amE = sm * aek;
-      const double alI = q[3 + DIM], alE = qe[3 + DIM];
-      const double jump = alI - alE;
-      const double ahat = 0.5 * (amI + amE) - A.pen[k] * A.GammaEps * jump;
-      const double Lf = A.lift[k];
-      double etav = 0.0;
-      if constexpr (VISC) {
-        const double mue = A.mu1 * alE + A.mu2 * (1.0 - alE);
-        etav = A.pen[k] * (0.5 * (g.mu + mue));
-      }
-#pragma unroll
-      for (int qi = 0; qi < NC; ++qi) {
-        const double FmI = sm * conv_flux<DIM>(q, pr, qi, k);
-        const double FmE = sm * conv_flux<DIM>(qe, pe, qi, k);
-        const double Fhat = 0.5 * (FmI + FmE) - 0.5 * lam * (qe[qi] - q[qi]);
-        const double sI = s_coef<DIM>(A, pr, qi), sE = s_coef<DIM>(A, pe, qi);
-        const double sbar = 0.5 * (sI + sE);
-        double t = (FmI - Fhat) + (sbar * ahat - sI * amI);
-        if constexpr (VISC) {
-          if (qi >= 2) {
-            double VmI, VmE, pen;
-            if (qi < 2 + DIM) {
-              const int j = qi - 2;
-              VmI = sm * (g.mu * g.S[j][k]);
-              VmE = sm * tek[j];
-              pen = etav * (pr.u[j] - pe.u[j]);
-            } else {
-              double tuI = 0.0, tuE = 0.0, du = 0.0;
-#pragma unroll
-              for (int j = 0; j < DIM; ++j) {
-                tuI += (g.mu * g.S[j][k]) * pr.u[j];
-                tuE += tek[j] * pe.u[j];
-                du += (pr.u[j] - pe.u[j]) * (0.5 * (pr.u[j] + pe.u[j]));
-              }
-              VmI = sm * tuI;
-              VmE = sm * tuE;
-              pen = etav * du;
-            }
-            const double Vhat = 0.5 * (VmI + VmE) - pen;
-            t += Vhat - VmI;
-          }
-        }
-        R[qi] += Lf * t;
-        symv[qi] = sm * sbar * A.GammaEps * jump;
-      }
-      const double KA = 0.5 * (lam - umI) * (alE - alI);
-      R[3 + DIM] += Lf * (KA + (ahat - amI));
-      symv[NC] = sm * A.GammaEps * jump;
-      R[4 + DIM] += Lf * (0.5 * (lam - umI) * (qe[4 + DIM] - q[4 + DIM]));
+      for (int f = 0; f < NF; ++f) R[f] += Rc[f];
     }
-    // SIPG symmetric term, spread along the normal line through each face node
-    // D[end][a] / (2 w_a J_k^2), end = 0 (low face) or 3 (high face)
-    const double wlo = sel4(akk, GLL.D[0][0] / GLL.w[0], GLL.D[0][1] / GLL.w[1], GLL.D[0][2] / GLL.w[2],
-                            GLL.D[0][3] / GLL.w[3]) * A.hJ2inv[k];
-    const double whi = sel4(akk, GLL.D[3][0] / GLL.w[0], GLL.D[3][1] / GLL.w[1], GLL.D[3][2] / GLL.w[2],
-                            GLL.D[3][3] / GLL.w[3]) * A.hJ2inv[k];
+    spread_sym<0, 2>(A, ak[0], symv, R);
+    // y-face results of this lane's node, from the lane that evaluated them
+    const bool yown = (ak[1] == 0) || (ak[1] == 3);
+    const int jl = (lane & 48) | ((ak[1] == 3 ? 2 : 1) + 4 * ak[0]);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const double r = __shfl(Rc[f], jl);
+      if (yown) R[f] += r;
+    }
 #pragma unroll
     for (int i = 0; i <= NC; ++i) {
-      double lo, hi;
-      if (k == 0) {
-        lo = line_end<0>(symv[i], akk, false);
-        hi = line_end<0>(symv[i], akk, true);
-      } else if (k == 1) {
-        lo = line_end<1>(symv[i], akk, false);
-        hi = line_end<1>(symv[i], akk, true);
-      } else {
-        lo = line_end<2>(symv[i], akk, false);
-        hi = line_end<2>(symv[i], akk, true);
+      const double v = __shfl(sv[i], jl);
+      symv[i] = yown ? v : 0.0;
+    }
+    spread_sym<1, 2>(A, ak[1], symv, R);
+  } else {
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      const int S = 1 << (2 * k);
+      const int akk = ak[k];
+      double symv[NC + 1];
+#pragma unroll
+      for (int i = 0; i <= NC; ++i) symv[i] = 0.0;
+      if ((akk == 0) || (akk == 3)) {
+        double Rc[NF], Sk[DIM];
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+          if constexpr (VISC) Sk[j] = g.S[j][k];
+          else Sk[j] = 0.0;
+        }
+        double gAk = 0.0, nhk = 0.0;
+        if constexpr (DIRI) {
+          gAk = g.gA[k];
+          nhk = g.nh[k];
+        }
+        face_flux<DIM, VISC, DIRI>(A, Us, Gin, k, akk == 3, bndk[k], enb[k], node + (3 - 2 * akk) * S,
+                                   face_index(node, k), q, pr, g.a[k], g.mu, Sk, gAk, nhk, Rc, symv);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) R[f] += Rc[f];
       }
-      const int f = (i < NC) ? i : 3 + DIM;
-      R[f] = fma(lo, wlo, fma(hi, whi, R[f]));
+      if (k == 0) spread_sym<0, DIM>(A, akk, symv, R);
+      else if (k == 1) spread_sym<(DIM > 1 ? 1 : 0), DIM>(A, akk, symv, R);
+      else spread_sym<(DIM > 2 ? 2 : 0), DIM>(A, akk, symv, R);
     }
   }
 
