@@ -43,6 +43,11 @@ WORKLOAD_DESC = {
     "waterair2d": "2D water droplet in air (density ratio 1000, P_inf 6000), 24x24 quads, p=3, FP64",
 }
 
+# default timed steps per workload: about 50 ms of GPU time on one MI355X, long
+# enough for the clocks to settle and the event timing to be stable
+DEFAULT_STEPS = {"drop1d": 2000, "drop2d": 1000, "shock2d": 200, "rt3d": 5, "adjoint2d": 1000,
+                 "waterair2d": 2000}
+
 
 def source_hash():
     h = hashlib.sha256()
@@ -222,8 +227,10 @@ def calibrate_copy(gib=2.0, reps=10):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: about 50 ms of GPU time for the workload)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps before the timed region (default: a quarter of --steps)")
     ap.add_argument("--workload", default="drop2d", choices=sorted(WORKLOAD_DESC))
     ap.add_argument("--cfl", type=float, default=0.1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -232,6 +239,10 @@ def main():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the mixed-precision, adjoint and kinematic measurements")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = DEFAULT_STEPS[args.workload]
+    if args.warmup is None:
+        args.warmup = max(10, args.steps // 4)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (--gpus 1); no multi-GPU path exists",

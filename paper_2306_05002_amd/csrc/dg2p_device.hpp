@@ -747,36 +747,50 @@ __device__ __forceinline__ double conv_flux_k(const double* q, const Prim& p, in
   return (q[2 + DIM] + p.P) * uk;
 }
 
+// Neighbour trace across a face: the state at node nodee of element en and
+// the face ingredients it published for face node fn of its side facing back
+// (a.e_kd, and the viscous traction when VISC).
+template <int DIM, bool VISC>
+__device__ __forceinline__ void face_load(const KArgs& A, const double* __restrict__ Us,
+                                          const double* __restrict__ Gin, int kd, int side, long long en, int nodee,
+                                          int fn, double* qn, double& an, double* tn) {
+  constexpr int NN = 1 << (2 * DIM);
+  constexpr int NF = DIM + 5;
+  constexpr int C = VISC ? 1 + DIM : 1;
+  constexpr int NFN = NN / 4;
+#pragma unroll
+  for (int f = 0; f < NF; ++f) qn[f] = Us[(f * A.E + en) * NN + nodee];
+  const long long gb = (long long)((2 * kd + 1 - side) * C) * A.E;
+  an = Gin[(gb + en) * NFN + fn];
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) tn[j] = VISC ? Gin[(gb + (long long)(1 + j) * A.E + en) * NFN + fn] : 0.0;
+}
+
 // Contributions of one face node of an element to that node: Rc[f] (lift
 // factor included) for every field, and the SIPG symmetric-term values symv
 // (conservative equations, then alpha) to be spread along the normal line.
 // Face normal axis kd, side 0 (low) / 1 (high).  The element's own trace:
 // q, p, a.e_kd (a_k), the viscous traction mu S[j][kd] (mu, Sk) and, for
 // Dirichlet ghosts, d_kd alpha and n_kd (gA_k, nh_k).  The neighbour's trace
-// is read from Us (element en, node nodee) with its ingredients from Gin
-// (face node fn), or built as the boundary ghost when bnd.
+// is qn with its ingredients an (a.e_kd) and tn (traction), as loaded by
+// face_load, or is built as the boundary ghost when bnd.
 template <int DIM, bool VISC, bool DIRI>
-__device__ __forceinline__ void face_flux(const KArgs& A, const double* __restrict__ Us,
-                                          const double* __restrict__ Gin, int kd, int side, bool bnd, long long en,
-                                          int nodee, int fn, const double* q, const Prim& pr, double a_k, double mu,
+__device__ __forceinline__ void face_flux(const KArgs& A, int kd, int side, bool bnd, const double* qn, double an,
+                                          const double* tn, const double* q, const Prim& pr, double a_k, double mu,
                                           const double* Sk, double gA_k, double nh_k, double* Rc, double* symv) {
-  constexpr int NN = 1 << (2 * DIM);
   constexpr int NF = DIM + 5;
   constexpr int NC = DIM + 3;
-  constexpr int C = VISC ? 1 + DIM : 1;
-  constexpr int NFN = NN / 4;
   const double sm = side ? 1.0 : -1.0;
   double qe[NF];
   double aek;
   double tek[DIM];
   if (!bnd) {
 #pragma unroll
-    for (int f = 0; f < NF; ++f) qe[f] = Us[(f * A.E + en) * NN + nodee];
-    const long long gb = (long long)((2 * kd + 1 - side) * C) * A.E;
-    aek = Gin[(gb + en) * NFN + fn];
+    for (int f = 0; f < NF; ++f) qe[f] = qn[f];
+    aek = an;
     if constexpr (VISC) {
 #pragma unroll
-      for (int j = 0; j < DIM; ++j) tek[j] = Gin[(gb + (long long)(1 + j) * A.E + en) * NFN + fn];
+      for (int j = 0; j < DIM; ++j) tek[j] = tn[j];
     }
   } else {
     const int kind = A.bc[kd][side];
@@ -947,15 +961,33 @@ __global__ __launch_bounds__(BLOCK, min_waves<DIM>()) void k_stage(KArgs A, Stag
     enb[k] = (isface && !bnd) ? e + (c - ec[k]) * estr : e;
     bndk[k] = bnd;
   }
-  double dt_fused = 0.0;
-  if constexpr (MODE == 1) {
-    if (io.dt_out) {  // uniform: the fused time step of a small grid
-      dt_fused = fused_dt(A, io.rate_in, io.dt_fixed, DIM);
-      if (blk == 0 && threadIdx.x == 0) {
-        *io.dt_out = dt_fused;
-        if (io.t) *io.t += dt_fused;
+  // 2D: the lane's face job (one face node of its quad, see the face pass)
+  // and the neighbour trace across it, loaded here so that the loads are in
+  // flight during the volume terms.
+  bool xjob = false, jbnd = false;
+  int jside = 0, onode = 0;
+  double qn[NF], an = 0.0, tn[DIM];
+  if constexpr (DIM == 2) {
+    xjob = (ak[0] == 0) || (ak[0] == 3);
+    jside = xjob ? (ak[0] == 3) : (ak[0] == 2);
+    onode = xjob ? node : ak[1] + (jside ? 12 : 0);
+    long long en;
+    if (xjob) {
+      en = enb[0];
+      jbnd = bndk[0];
+    } else {
+      long long c = ec[1] + (jside ? 1 : -1);
+      if (c < 0 || c >= A.N[1]) {
+        if ((jside ? A.bc[1][1] : A.bc[1][0]) == DG2P_BC_PERIODIC)
+          c = (c < 0) ? A.N[1] - 1 : 0;
+        else
+          jbnd = true;
       }
+      en = jbnd ? e : e + (c - ec[1]) * A.N[0];
     }
+    const int nodee = xjob ? node + (3 - 2 * ak[0]) : onode + (jside ? -12 : 12);
+    const int fn = xjob ? (node >> 2) : ak[1];
+    face_load<2, VISC>(A, Us, io.Gin, xjob ? 0 : 1, jside, en, nodee, fn, qn, an, tn);
   }
   Prim pr;
   closure<DIM>(A, q, pr);
@@ -1041,9 +1073,6 @@ __global__ __launch_bounds__(BLOCK, min_waves<DIM>()) void k_stage(KArgs A, Stag
     // y-face at node (a_y, 0) ((a_y, 3)).  The owner node's trace comes from
     // its lane and the results go back to it by lane exchanges, so no face is
     // evaluated on half-idle lanes.
-    const bool xjob = (ak[0] == 0) || (ak[0] == 3);
-    const int jside = xjob ? (ak[0] == 3) : (ak[0] == 2);
-    const int onode = xjob ? node : ak[1] + (jside ? 12 : 0);
     const int olane = (lane & 48) | onode;
     double qo[NF];
 #pragma unroll
@@ -1072,28 +1101,8 @@ __global__ __launch_bounds__(BLOCK, min_waves<DIM>()) void k_stage(KArgs A, Stag
       gAk = xjob ? g.gA[0] : ga1;
       nhk = xjob ? g.nh[0] : nh1;
     }
-    // neighbour across the job's face
-    long long en;
-    bool bnd;
-    if (xjob) {
-      en = enb[0];
-      bnd = bndk[0];
-    } else {
-      long long c = ec[1] + (jside ? 1 : -1);
-      bnd = false;
-      if (c < 0 || c >= A.N[1]) {
-        if ((jside ? A.bc[1][1] : A.bc[1][0]) == DG2P_BC_PERIODIC)
-          c = (c < 0) ? A.N[1] - 1 : 0;
-        else
-          bnd = true;
-      }
-      en = bnd ? e : e + (c - ec[1]) * A.N[0];
-    }
-    const int nodee = xjob ? node + (3 - 2 * ak[0]) : onode + (jside ? -12 : 12);
-    const int fn = xjob ? (node >> 2) : ak[1];
     double Rc[NF], sv[NC + 1];
-    face_flux<2, VISC, DIRI>(A, Us, Gin, xjob ? 0 : 1, jside, bnd, en, nodee, fn, qo, po, ao, mu, Sk, gAk, nhk,
-                             Rc, sv);
+    face_flux<2, VISC, DIRI>(A, xjob ? 0 : 1, jside, jbnd, qn, an, tn, qo, po, ao, mu, Sk, gAk, nhk, Rc, sv);
     double symv[NC + 1];
 #pragma unroll
     for (int i = 0; i <= NC; ++i) symv[i] = xjob ? sv[i] : 0.0;
@@ -1136,8 +1145,10 @@ __global__ __launch_bounds__(BLOCK, min_waves<DIM>()) void k_stage(KArgs A, Stag
           gAk = g.gA[k];
           nhk = g.nh[k];
         }
-        face_flux<DIM, VISC, DIRI>(A, Us, Gin, k, akk == 3, bndk[k], enb[k], node + (3 - 2 * akk) * S,
-                                   face_index(node, k), q, pr, g.a[k], g.mu, Sk, gAk, nhk, Rc, symv);
+        double qk[NF], ank, tk[DIM];
+        face_load<DIM, VISC>(A, Us, Gin, k, akk == 3, enb[k], node + (3 - 2 * akk) * S, face_index(node, k), qk,
+                             ank, tk);
+        face_flux<DIM, VISC, DIRI>(A, k, akk == 3, bndk[k], qk, ank, tk, q, pr, g.a[k], g.mu, Sk, gAk, nhk, Rc, symv);
 #pragma unroll
         for (int f = 0; f < NF; ++f) R[f] += Rc[f];
       }
@@ -1147,6 +1158,17 @@ __global__ __launch_bounds__(BLOCK, min_waves<DIM>()) void k_stage(KArgs A, Stag
     }
   }
 
+  // the fused time step of a small grid (uniform branch), needed from here on
+  double dt_fused = 0.0;
+  if constexpr (MODE == 1) {
+    if (io.dt_out) {
+      dt_fused = fused_dt(A, io.rate_in, io.dt_fixed, DIM);
+      if (blk == 0 && threadIdx.x == 0) {
+        *io.dt_out = dt_fused;
+        if (io.t) *io.t += dt_fused;
+      }
+    }
+  }
   const long long o = e * NN + node;
   const long long fs = A.E * NN;
   if constexpr (MODE == 0) {
