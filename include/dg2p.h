@@ -64,7 +64,17 @@ typedef enum {
   DG2P_BC_SLIP_WALL = 1,  /* mirror: normal momentum and normal gradients negated */
   DG2P_BC_DIRICHLET = 2,  /* prescribed (q1, q2, rho u, rho E, alpha); interior psi
                              and gradients */
-  DG2P_BC_EXTRAPOLATE = 3 /* ghost = interior (state and gradients) */
+  DG2P_BC_EXTRAPOLATE = 3, /* ghost = interior (state and gradients) */
+  DG2P_BC_NO_SLIP = 4,     /* wall with zero velocity: whole momentum negated,
+                              normal gradients of alpha and psi negated, the
+                              velocity gradient (wall shear) kept */
+  DG2P_BC_RIEMANN = 5      /* Riemann-invariant far field with zero velocity
+                              and pressure bc_state[0] (Section "Rayleigh-Taylor
+                              instability", top boundary): outgoing invariant
+                              u.n + 2 xi c from the interior, incoming -2 xi c_far
+                              from (u = 0, P = bc_state[0], interior density);
+                              interior partial densities, tangential velocity,
+                              alpha, psi and gradients */
 } dg2p_bc;
 
 typedef enum {
@@ -97,8 +107,9 @@ typedef struct {
   int n_elem[3];             /* elements per axis, >= 1 */
   double lo[3], hi[3];       /* box corners, hi > lo */
   int bc[3][2];              /* dg2p_bc per axis and side (0 = low, 1 = high) */
-  double bc_state[3][2][8];  /* Dirichlet conserved state per side (first d+4
-                                entries used: q1, q2, rho u, rho E, alpha) */
+  double bc_state[3][2][8];  /* per side: Dirichlet conserved state (first d+4
+                                entries: q1, q2, rho u, rho E, alpha); Riemann
+                                far-field pressure in entry 0 (must be > 0) */
 } dg2p_mesh_desc;
 
 /* Physical and numerical parameters (Section "Five equation model"). */

@@ -18,7 +18,7 @@ import torch
 
 from .gll import gll_nodes_weights, derivative_matrix
 
-BC_KINDS = ("periodic", "slip_wall", "dirichlet", "extrapolate")
+BC_KINDS = ("periodic", "slip_wall", "dirichlet", "extrapolate", "no_slip", "riemann")
 
 
 class OracleMesh:

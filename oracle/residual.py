@@ -36,7 +36,12 @@ Readings where the paper is silent (all also listed in the design notes):
     delta^2) - delta, delta = grad_reg;
   * boundary ghosts: slip wall mirrors the state and gradients in the
     normal direction; Dirichlet prescribes (q1, q2, rho u, rho E, alpha) and
-    keeps the interior psi and gradients; extrapolation copies the interior.
+    keeps the interior psi and gradients; extrapolation copies the interior;
+    no-slip wall negates the whole momentum, mirrors the scalar gradients and
+    keeps the velocity gradient; the Riemann-invariant boundary (zero
+    velocity and pressure P_b outside, Section "Rayleigh-Taylor
+    instability") builds its ghost state from the two characteristic
+    invariants (_riemann_ghost) and keeps the interior gradients.
 
 Every element evaluates all of its own faces (the neighbour's element-local
 gradients are recomputed from the neighbour's nodal data), so any subset of
@@ -122,20 +127,65 @@ def _trace_raw(raw, k, idx):
     return {key: _trace(v, k, idx) for key, v in raw.items()}
 
 
-def _ghost(rawI, kind, k, d, bc_vals):
+def _riemann_ghost(Q, k, side, d, P_b, prm):
+    """Far-field ghost state of a Riemann-invariant boundary with zero velocity
+    and pressure P_b outside (Section "Rayleigh-Taylor instability": top
+    boundary).  With n the outward normal and the mixture treated as a
+    stiffened gas at the interior composition (gamma - 1 = 1/xi), the outgoing
+    invariant J+ = u.n + 2 xi c comes from the interior and the incoming one
+    J- = -2 xi c_far from the far field (u = 0, P = P_b, interior density);
+    the boundary state has u.n = (J+ + J-)/2 and c = (J+ - J-)/(4 xi), the
+    pressure that gives this c at the interior density, and interior partial
+    densities, tangential velocity, alpha and psi."""
+    pr = primitives(Q, d, prm)
+    rho, xi, pi = pr["rho"], pr["xi"], pr["pi"]
+    sm = 1.0 if side == 1 else -1.0
+    un = sm * pr["u"][k]
+    c_far = torch.sqrt(((1.0 + xi) * P_b + pi) / (xi * rho))
+    j_out = un + 2.0 * xi * pr["c"]
+    j_in = -2.0 * xi * c_far
+    un_b = 0.5 * (j_out + j_in)
+    c_b = (j_out - j_in) / (4.0 * xi)
+    P_g = (xi * rho * c_b * c_b - pi) / (1.0 + xi)
+    u_g = pr["u"].clone()
+    u_g[k] = u_g[k] + sm * (un_b - un)
+    G = Q.clone()
+    for j in range(d):
+        G[2 + j] = rho * u_g[j]
+    G[2 + d] = xi * P_g + pi + 0.5 * rho * (u_g * u_g).sum(0)
+    return G
+
+
+def _ghost(rawI, kind, k, side, d, bc_vals, prm):
     """Ghost trace for a non-periodic boundary face, built from the interior trace."""
     if kind == "extrapolate":
         return dict(rawI)
-    if kind == "slip_wall":
+    if kind in ("slip_wall", "no_slip"):
+        # mirror image: scalar gradients have their normal component negated.
+        # Slip wall: the normal momentum flips and the velocity gradient is
+        # mirrored too (no tangential stress); no-slip wall: the whole momentum
+        # flips (zero velocity on the wall) and the velocity gradient is kept
+        # (the wall takes the interior shear stress).
         Q = rawI["Q"].clone()
-        Q[2 + k] = -Q[2 + k]
+        if kind == "slip_wall":
+            Q[2 + k] = -Q[2 + k]
+        else:
+            for j in range(d):
+                Q[2 + j] = -Q[2 + j]
         sgn = torch.ones(d, dtype=torch.float64)
         sgn[k] = -1.0
         shp = (d,) + (1,) * (rawI["gA"].dim() - 1)
         g = dict(Q=Q, gA=rawI["gA"] * sgn.view(shp), gP=rawI["gP"] * sgn.view(shp))
         if "gU" in rawI:
-            shp2 = (d, d) + (1,) * (rawI["gU"].dim() - 2)
-            g["gU"] = rawI["gU"] * (sgn[:, None] * sgn[None, :]).view(shp2)
+            if kind == "slip_wall":
+                shp2 = (d, d) + (1,) * (rawI["gU"].dim() - 2)
+                g["gU"] = rawI["gU"] * (sgn[:, None] * sgn[None, :]).view(shp2)
+            else:
+                g["gU"] = rawI["gU"]
+        return g
+    if kind == "riemann":
+        g = dict(rawI)
+        g["Q"] = _riemann_ghost(rawI["Q"], k, side, d, float(bc_vals[0]), prm)
         return g
     if kind == "dirichlet":
         Q = rawI["Q"].clone()
@@ -274,7 +324,7 @@ def _rhs_batch(U, mesh, prm, el):
             rawE = _trace_raw(_raw(Y, mesh, prm), k, idxE)
             kind = mesh.bc[k][side]
             if kind != "periodic" and bool(bnd.any()):
-                ghost = _ghost(rawI, kind, k, d, mesh.bc_state.get((k, side)))
+                ghost = _ghost(rawI, kind, k, side, d, mesh.bc_state.get((k, side)), prm)
                 rawE = _where_raw(bnd, ghost, rawE)
             I = _pointwise(rawI, d, prm)
             E = _pointwise(rawE, d, prm)

@@ -168,10 +168,12 @@ struct TimedLaunch {
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 bool viscous(const dg2p_params* p) { return p->mu[0] != 0.0 || p->mu[1] != 0.0; }
+// boundary kinds whose ghost needs the side's bc_state (compiled in only
+// where a mesh has them)
 bool has_dirichlet(const dg2p_mesh_s* m) {
   for (int k = 0; k < m->dim; ++k)
     for (int s = 0; s < 2; ++s)
-      if (m->desc.bc[k][s] == DG2P_BC_DIRICHLET) return true;
+      if (m->desc.bc[k][s] == DG2P_BC_DIRICHLET || m->desc.bc[k][s] == DG2P_BC_RIEMANN) return true;
   return false;
 }
 
@@ -564,9 +566,12 @@ int dg2p_create_mesh(const dg2p_mesh_desc* desc, dg2p_mesh* out) {
     if (desc->n_elem[k] < 1) return fail(DG2P_EINVAL, "n_elem must be >= 1");
     if (!(desc->hi[k] > desc->lo[k]) || !std::isfinite(desc->hi[k] - desc->lo[k]))
       return fail(DG2P_EINVAL, "hi must exceed lo");
-    for (int s = 0; s < 2; ++s)
-      if (desc->bc[k][s] < DG2P_BC_PERIODIC || desc->bc[k][s] > DG2P_BC_EXTRAPOLATE)
+    for (int s = 0; s < 2; ++s) {
+      if (desc->bc[k][s] < DG2P_BC_PERIODIC || desc->bc[k][s] > DG2P_BC_RIEMANN)
         return fail(DG2P_EINVAL, "unknown boundary kind");
+      if (desc->bc[k][s] == DG2P_BC_RIEMANN && !(desc->bc_state[k][s][0] > 0.0))
+        return fail(DG2P_EINVAL, "Riemann boundary needs a far-field pressure > 0 in bc_state[0]");
+    }
     if ((desc->bc[k][0] == DG2P_BC_PERIODIC) != (desc->bc[k][1] == DG2P_BC_PERIODIC))
       return fail(DG2P_EINVAL, "periodic must be set on both sides of an axis");
     E *= desc->n_elem[k];

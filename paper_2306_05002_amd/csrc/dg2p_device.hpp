@@ -801,18 +801,45 @@ __device__ __forceinline__ void face_flux(const KArgs& A, int kd, int side, bool
 #pragma unroll
       for (int j = 0; j < DIM; ++j) tek[j] = mu * Sk[j];
     }
-    if (kind == DG2P_BC_SLIP_WALL) {
+    if (kind == DG2P_BC_SLIP_WALL || kind == DG2P_BC_NO_SLIP) {
+      // mirror image; the slip wall flips the normal momentum and mirrors the
+      // shear (tangential traction negated), the no-slip wall flips the whole
+      // momentum and keeps the shear
+      const bool slip = kind == DG2P_BC_SLIP_WALL;
 #pragma unroll
       for (int j = 0; j < DIM; ++j)
-        if (j == kd) qe[2 + j] = -q[2 + j];
+        if (!slip || j == kd) qe[2 + j] = -q[2 + j];
       aek = -a_k;
       if constexpr (VISC) {
 #pragma unroll
         for (int j = 0; j < DIM; ++j)
-          if (j != kd) tek[j] = -tek[j];
+          if (slip && j != kd) tek[j] = -tek[j];
       }
     }
     if constexpr (DIRI) {
+      if (kind == DG2P_BC_RIEMANN) {
+        // far field at rest with pressure P_b: invariants u.n +- 2 xi c of the
+        // mixture stiffened gas at the interior composition and density
+        const double al = q[3 + DIM];
+        const double xi = al * A.xi1 + (1.0 - al) * A.xi2;
+        const double pim = al * A.pi1 + (1.0 - al) * A.pi2;
+        const double Pb = A.bcs[kd][side][0];
+        const double un = sm * pick<DIM>(pr.u, kd);
+        const double cfar = sqrt(((1.0 + xi) * Pb + pim) / (xi * pr.rho));
+        const double jout = un + 2.0 * xi * pr.c;
+        const double jin = -2.0 * xi * cfar;
+        const double unb = 0.5 * (jout + jin);
+        const double cb = (jout - jin) / (4.0 * xi);
+        const double Pg = (xi * pr.rho * cb * cb - pim) / (1.0 + xi);
+        double k2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+          const double ug = pr.u[j] + (j == kd ? sm * (unb - un) : 0.0);
+          qe[2 + j] = pr.rho * ug;
+          k2 += ug * ug;
+        }
+        qe[2 + DIM] = xi * Pg + pim + 0.5 * pr.rho * k2;
+      }
       if (kind == DG2P_BC_DIRICHLET) {
 #pragma unroll
         for (int f = 0; f < 4 + DIM; ++f) qe[f] = A.bcs[kd][side][f];

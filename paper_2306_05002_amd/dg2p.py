@@ -22,7 +22,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, EHIP, ENONPHYS, EUNSUPPORTED, EWORKSPACE = 0, -1, -2, -3, -4, -5
-BC = {"periodic": 0, "slip_wall": 1, "dirichlet": 2, "extrapolate": 3}
+BC = {"periodic": 0, "slip_wall": 1, "dirichlet": 2, "extrapolate": 3, "no_slip": 4, "riemann": 5}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
 OP_RHS, OP_RK_STEP, OP_MAX_DT, OP_MONITORS, OP_RHS_VJP, OP_RK_STEP_VJP, OP_ADVANCE = range(7)
 OP_KIN_RHS, OP_KIN_RK4, OP_KIN_AUX = 7, 8, 9
@@ -343,7 +343,7 @@ def mesh_from_config(cfg, params=None):
     """Mesh for a workloads configuration; Dirichlet states are mapped to
     conserved variables with the library's own initial-condition kernel."""
     d = cfg["dim"]
-    bc_state = {}
+    bc_state = {key: list(v) for key, v in cfg.get("bc_state", {}).items()}
     if cfg.get("bc_prim"):
         P = make_params(cfg["params"]) if params is None else params
         probe = Mesh(d, (1,) * d, (0.0,) * d, (1.0,) * d)

@@ -21,9 +21,14 @@ Configurations (all p = 3, i.e. four GLL nodes per direction):
   waterair2d the paper's water droplet (R 25/89) in air, 24 x 24, density
              ratio 1000 (rho 1e-3 / 1), P_inf 0 / 6000, u = (5, 5), P = 1,
              Gamma 5, five advection periods (t = 1)
+  bubble2d   the paper's rising bubble: R 0.25 at (0, 0.5) in [-0.5, 0.5] x
+             [0, 2], 20 x 40, rho_1/rho_2 = mu_1/mu_2 = 10, Re 35, Eo 10;
+             no-slip bottom, Riemann-invariant top (zero velocity, P 1000),
+             slip side walls
 Phase 1 is air (gamma 1.4, P_inf 0), phase 2 water-like (gamma 4.4,
-P_inf 0.6); alpha is the volume fraction of phase 1 and psi increases
-towards phase 1, alpha = 1 / (1 + exp(-psi / eps)).
+P_inf 0.6), except in bubble2d where phase 1 is the heavy surrounding
+liquid; alpha is the volume fraction of phase 1 and psi increases towards
+phase 1, alpha = 1 / (1 + exp(-psi / eps)).
 """
 
 import math
@@ -31,7 +36,7 @@ import math
 import numpy as np
 
 ORDER = 3
-NAMES = ("drop1d", "drop2d", "shock2d", "rt3d", "adjoint2d", "waterair2d")
+NAMES = ("drop1d", "drop2d", "shock2d", "rt3d", "adjoint2d", "waterair2d", "bubble2d")
 FULL_ELEMS = {
     "drop1d": (100,),
     "drop2d": (128, 128),
@@ -39,6 +44,7 @@ FULL_ELEMS = {
     "rt3d": (96, 96, 96),
     "adjoint2d": (128, 128),
     "waterair2d": (24, 24),
+    "bubble2d": (20, 40),
 }
 
 
@@ -106,6 +112,16 @@ def config(name, n_elem=None):
                    bc=[("periodic", "periodic")] * 2, t_end=1.0)
         base.update(rho0=(1e-3, 1.0), pinf=(0.0, 6.0e3), Gamma=5.0)
         cfg.update(steps=200)
+    elif name == "bubble2d":
+        # Re = rho_1 d^(3/2) |g|^(1/2) / mu_1 = 35 and Eo = 4 rho_1 |g| R^2 / sigma
+        # = 10 with rho_1 = 1000, |g| = 0.98, d = 2R = 0.5; stiffened gases with
+        # a Mach number below 0.1 at the rise velocity
+        cfg.update(dim=2, lo=(-0.5, 0.0), hi=(0.5, 2.0),
+                   bc=[("slip_wall", "slip_wall"), ("no_slip", "riemann")],
+                   t_end=3.0, steps=200, p_top=1000.0, radius=0.25, centre=(0.0, 0.5))
+        base.update(gamma=(4.4, 1.4), pinf=(6.0e4, 0.0), rho0=(1000.0, 100.0),
+                    mu=(10.0, 1.0), sigma=24.5, g=(0.0, -0.98, 0.0))
+        cfg["bc_state"] = {(1, 1): [cfg["p_top"]]}
     elif name == "rt3d":
         cfg.update(dim=3, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
                    bc=[("periodic", "periodic")] * 2 + [("slip_wall", "slip_wall")],
@@ -120,6 +136,7 @@ def config(name, n_elem=None):
     base["eps"] = (0.5 * h) if name == "waterair2d" else 0.5 * h / (p + 1)
     cfg["params"] = base
     cfg.setdefault("bc_prim", {})
+    cfg.setdefault("bc_state", {})
     return cfg
 
 
@@ -192,6 +209,14 @@ def primitive_fields(cfg, coords, variant=None):
         rho1 = w * rho_post + (1.0 - w) * 1.0
         u[0] = w * u_post
         P = w * p_post + (1.0 - w) * 1.0
+    elif name == "bubble2d":
+        cx, cy = cfg["centre"]
+        psi = np.sqrt((X[0] - cx) ** 2 + (X[1] - cy) ** 2) - cfg["radius"]
+        # heavy-liquid column under P_top, plus the Laplace jump sigma / R inside
+        # the bubble
+        inside = 1.0 - _sigmoid(psi / eps)
+        P = (cfg["p_top"] + r1 * (-prm["g"][1]) * (cfg["hi"][1] - X[1])
+             + prm["sigma"] / cfg["radius"] * inside)
     elif name == "rt3d":
         x, y, z = X[0], X[1], X[2]
         eta = (0.5 + 0.02 * np.cos(2 * math.pi * x) * np.cos(2 * math.pi * y)

@@ -17,7 +17,7 @@ def oracle_setup(name, n_elem=None, variant=None, bc=None, **param_over):
     cfg["params"] = {**cfg["params"], **param_over}   # overrides reach the initial state too
     prm = oracle.Params(**cfg["params"])
     d = cfg["dim"]
-    bc_state = {}
+    bc_state = {key: torch.tensor(v, dtype=torch.float64) for key, v in cfg.get("bc_state", {}).items()}
     for key, bp in cfg.get("bc_prim", {}).items():
         t = lambda v: torch.tensor([float(v)], dtype=torch.float64)
         Qb = oracle.prim_to_cons(t(bp["alpha"]), t(bp["psi"]), t(bp["rho1"]),

@@ -35,7 +35,7 @@ def test_version_and_status_strings():
     assert dg2p._lib.dg2p_status_string(-1).decode() == "DG2P_EINVAL"
 
 
-@pytest.mark.parametrize("bad", ["dim", "order", "n_elem", "box", "bc", "periodic_pair"])
+@pytest.mark.parametrize("bad", ["dim", "order", "n_elem", "box", "bc", "periodic_pair", "riemann_pressure"])
 def test_create_mesh_rejects_bad_descriptors(bad):
     kw = dict(dim=2, n_elem=(4, 4), lo=(0, 0), hi=(1, 1), bc=None, order=3)
     if bad == "dim":
@@ -48,12 +48,20 @@ def test_create_mesh_rejects_bad_descriptors(bad):
         kw["hi"] = (1, -1)
     elif bad == "bc":
         kw["bc"] = [(0, 0), (7, 7)]
+    elif bad == "riemann_pressure":    # a Riemann side needs its far-field pressure
+        kw["bc"] = [("slip_wall", "slip_wall"), ("no_slip", "riemann")]
     else:
         kw["bc"] = [("periodic", "slip_wall"), ("periodic", "periodic")]
     with pytest.raises(dg2p.Dg2pError) as ei:
         dg2p.Mesh(kw["dim"], kw["n_elem"], kw["lo"], kw["hi"], kw["bc"], order=kw["order"])
     want = dg2p.EUNSUPPORTED if bad == "order" else dg2p.EINVAL
     assert ei.value.status == want
+
+
+def test_create_mesh_accepts_wall_and_riemann_kinds():
+    m = dg2p.Mesh(2, (4, 8), (-0.5, 0), (0.5, 2), [("slip_wall", "slip_wall"), ("no_slip", "riemann")],
+                  bc_state={(1, 1): [1000.0]})
+    assert m.E == 32
 
 
 def test_params_validation():

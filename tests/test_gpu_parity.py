@@ -65,6 +65,8 @@ SMALL = [
     ("rt3d", (5, 4, 6), None),         # viscous + CSF + gravity + slip walls
     ("rt3d", (1, 1, 2), None),
     ("waterair2d", (6, 5), None),      # density ratio 1000, P_inf 6000
+    ("bubble2d", (4, 8), None),        # no-slip bottom, Riemann top, slip sides; viscous + CSF + gravity
+    ("bubble2d", (5, 7), None),        # ragged: 35 elements
 ]
 
 
@@ -81,7 +83,8 @@ def test_rhs_parity(name, ne, variant):
 
 
 @pytest.mark.parametrize("name,ne,steps", [("drop1d", None, 100), ("drop2d", (8, 8), 30),
-                                           ("rt3d", (4, 4, 4), 10), ("adjoint2d", (8, 8), 20)])
+                                           ("rt3d", (4, 4, 4), 10), ("adjoint2d", (8, 8), 20),
+                                           ("bubble2d", (4, 8), 20)])
 def test_rhs_parity_evolved_state(name, ne, steps):
     """Parity on a state the oracle has advanced (not an initial condition)."""
     cfg, om, prm, U0, mesh, P = gpu_case(name, ne, "noisy_u" if name == "drop1d" else None)
@@ -96,7 +99,7 @@ def test_rhs_parity_evolved_state(name, ne, steps):
 
 
 @pytest.mark.parametrize("name,ne", [("drop1d", (37,)), ("drop2d", (7, 5)), ("shock2d", (13, 7)),
-                                     ("adjoint2d", (6, 5)), ("rt3d", (3, 4, 5))])
+                                     ("adjoint2d", (6, 5)), ("rt3d", (3, 4, 5)), ("bubble2d", (5, 9))])
 def test_rk_step_and_dt_parity(name, ne):
     cfg, om, prm, U0, mesh, P = gpu_case(name, ne)
     dg = _dg()
@@ -210,7 +213,8 @@ def test_interface_equilibrium_on_gpu():
 
 
 @pytest.mark.parametrize("name,ne,steps", [("drop2d", (9, 7), 4), ("rt3d", (3, 3, 4), 3),
-                                           ("shock2d", (10, 6), 3), ("drop1d", (21,), 5)])
+                                           ("shock2d", (10, 6), 3), ("drop1d", (21,), 5),
+                                           ("bubble2d", (5, 9), 4)])
 def test_advance_matches_rk_steps(name, ne, steps):
     """dg2p_advance (device dt, carried face ingredients, fused records) gives
     the same states as dg2p_max_dt + dg2p_rk_step repeated, bit for bit, and
@@ -406,7 +410,7 @@ def test_vjp_rejects_unsupported():
     assert ei.value.status == dg.EUNSUPPORTED
 
 
-FULL = ["drop2d", "shock2d", "adjoint2d", "rt3d"]
+FULL = ["drop2d", "shock2d", "adjoint2d", "rt3d", "bubble2d"]
 
 
 def _sample_elements(cfg, n=48, seed=0):
@@ -446,3 +450,34 @@ def test_full_size_sampled_parity(name):
     assert abs(float(dt.cpu()) - 0.1 / rate) <= TOL * 0.1 / rate
     del Rg, Ud
     torch.cuda.empty_cache()
+
+
+def test_rising_bubble_rises():
+    """The paper's rising bubble (no-slip bottom, Riemann-invariant top, slip
+    sides; 20 x 40, p = 3) over t = 0.5: no non-physical state, the bubble's
+    centre of gravity moves up and its mean vertical velocity is positive
+    (a qualitative check: the paper's reference curves are not reproduced)."""
+    cfg = workloads.config("bubble2d")
+    dg = _dg()
+    P = dg.make_params(cfg["params"])
+    mesh = dg.mesh_from_config(cfg, P)
+    X = mesh.node_coords()
+    U = dg.prim_to_cons(mesh, P, dg.prim_tensor(workloads.primitive_fields(cfg, X), 2))
+    W = torch.tensor(mesh.node_weights(), device="cuda")     # tensor-product GLL weights per node
+    y = torch.tensor(X[1], device="cuda")
+
+    def centre(U):
+        b = (1.0 - U[5]) * W          # bubble (phase 2) volume fraction, quadrature weights
+        rho = U[0] + U[1]
+        return float((b * y).sum() / b.sum()), float((b * U[3] / rho).sum() / b.sum())
+
+    y0, v0 = centre(U)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    mon = torch.zeros(dg.MONITOR_DOUBLES, dtype=torch.float64, device="cuda")
+    while float(t.cpu()) < 0.5:
+        dg.advance(mesh, P, U, 200, cfl=0.1, t=t, mon=mon)
+        m = dg.decode_monitors(mon, mesh.nf)
+        assert m["nonphys"] == 0
+    y1, v1 = centre(U)
+    print("t", float(t.cpu()), "y_c", y0, "->", y1, "v_c", v0, "->", v1)
+    assert y1 > y0 + 0.03 and v1 > 0.05
