@@ -41,12 +41,15 @@ WORKLOAD_DESC = {
     "rt3d": "3D heavy-over-light box, 96^3 hexahedra, p=3, viscous + CSF + gravity, FP64",
     "adjoint2d": "2D droplet 128x128 p=3, viscous + CSF, FP64 forward",
     "waterair2d": "2D water droplet in air (density ratio 1000, P_inf 6000), 24x24 quads, p=3, FP64",
+    "bubble2d": "2D rising bubble, 20x40 quads, p=3, rho/mu ratio 10, Re 35, Eo 10, no-slip bottom, "
+                "Riemann top, slip sides, FP64",
+    "rt2d": "2D Rayleigh-Taylor, 20x80 quads, p=3, At 0.5, Re 3000, no-slip bottom, Riemann top, slip sides, FP64",
 }
 
 # default timed steps per workload: about 50 ms of GPU time on one MI355X, long
 # enough for the clocks to settle and the event timing to be stable
 DEFAULT_STEPS = {"drop1d": 2000, "drop2d": 1000, "shock2d": 200, "rt3d": 5, "adjoint2d": 1000,
-                 "waterair2d": 2000}
+                 "waterair2d": 2000, "bubble2d": 2000, "rt2d": 1000}
 
 
 def source_hash():
@@ -185,6 +188,72 @@ def waterair_section():
     return {"workload": "waterair2d: water droplet R=25/89 in air, 24x24 p=3, rho 1e-3/1, P_inf 0/6000, "
                         "u=(5,5), eps=h/2, Gamma=5, five periods (t=1), fixed dt",
             "steps": ns, "unit": "DOF-updates/s", "runs": runs}
+
+
+def walls_section():
+    """The paper's two wall-bounded cases with the no-slip bottom, the
+    Riemann-invariant top (zero velocity, constant pressure) and slip sides,
+    run to their final times in FP64 with the device time step (qualitative:
+    the comparison curves are not reproduced here).  Rising bubble: centre of
+    gravity and mean rise velocity of the bubble; Rayleigh-Taylor: the highest
+    point of the light fluid and the lowest of the heavy fluid (nodal
+    alpha = 1/2 crossings), against t* = t / sqrt(d / (|g| At))."""
+    import torch
+    from paper_2306_05002_amd import dg2p, workloads
+    out = {}
+    for name in ("bubble2d", "rt2d"):
+        cfg = workloads.config(name)
+        P = dg2p.make_params(cfg["params"])
+        mesh = dg2p.mesh_from_config(cfg, P)
+        X = mesh.node_coords()
+        U = dg2p.prim_to_cons(mesh, P, dg2p.prim_tensor(workloads.primitive_fields(cfg, X), 2))
+        W = torch.tensor(mesh.node_weights(), device="cuda")
+        y = torch.tensor(X[1], device="cuda")
+        dof = mesh.E * mesh.nn * mesh.nf
+        t = torch.zeros(1, dtype=torch.float64, device="cuda")
+        dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+        mon = torch.zeros(dg2p.MONITOR_DOUBLES, dtype=torch.float64, device="cuda")
+        t_scale = 1.0 if name == "bubble2d" else math.sqrt(2.0)     # t* = t / sqrt(d / (|g| At))
+        dt0 = None
+        marks = [0.5 * i for i in range(1, 7)]
+        rows, steps, ms = [], 0, 0.0
+        chunk = 250
+        while float(t.cpu()) < cfg["t_end"] * (1.0 - 1e-12):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            dg2p.advance(mesh, P, U, chunk, cfl=0.1, t=t, dt_last=dt, mon=mon)
+            e1.record()
+            torch.cuda.synchronize()
+            ms += e0.elapsed_time(e1)
+            steps += chunk
+            tn = float(t.cpu())
+            dtn = float(dt.cpu())
+            dt0 = dtn if dt0 is None else dt0
+            if (steps >= 200000 or not math.isfinite(tn) or not dtn > 1e-2 * dt0
+                    or dg2p.decode_monitors(mon, mesh.nf)["nonphys"]):
+                # the time step collapsed or a state left the physical domain
+                rows.append({"stopped_at_t": tn, "steps": steps, "dt": dtn, "dt_initial": dt0})
+                break
+            if not marks or tn / t_scale < marks[0]:
+                continue
+            while marks and tn / t_scale >= marks[0]:
+                marks.pop(0)
+            m = dg2p.decode_monitors(mon, mesh.nf)
+            a = U[5]
+            if name == "bubble2d":
+                b = (1.0 - a) * W
+                rho = U[0] + U[1]
+                rows.append({"t": tn, "y_c": float((b * y).sum() / b.sum()),
+                             "v_c": float((b * U[3] / rho).sum() / b.sum()), "nonphys": m["nonphys"]})
+            else:
+                light = a > 0.5
+                rows.append({"t_star": tn / t_scale, "top": float(y[light].max()),
+                             "bottom": float(y[~light].min()), "nonphys": m["nonphys"]})
+        out[name] = {"workload": f"{name}: {WORKLOAD_DESC[name]}", "steps": steps, "series": rows,
+                     "ms_per_step": ms / steps, "value": 3.0 * dof * steps / (ms * 1e-3),
+                     "unit": "DOF-updates/s"}
+    return out
 
 
 # steps after which the mixed-precision forms' field errors are stated
@@ -387,9 +456,11 @@ def main():
 
     kinematic = None
     waterair = None
+    walls = None
     if not args.no_variants:
         kinematic = kinematic_section()
         waterair = waterair_section()
+        walls = walls_section()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -439,6 +510,7 @@ def main():
         "adjoint": adjoint,
         "kinematic": kinematic,
         "water_air_droplet": waterair,
+        "wall_bounded": walls,
         "cpu_baseline": cpu,
         "monitors": {"nonphys": mon["nonphys"], "min_alpha": mon["min_alpha"],
                      "max_alpha": mon["max_alpha"]},

@@ -25,6 +25,9 @@ Configurations (all p = 3, i.e. four GLL nodes per direction):
              [0, 2], 20 x 40, rho_1/rho_2 = mu_1/mu_2 = 10, Re 35, Eo 10;
              no-slip bottom, Riemann-invariant top (zero velocity, P 1000),
              slip side walls
+  rt2d       the paper's 2D Rayleigh-Taylor case: [0, 1] x [0, 4], 20 x 80,
+             interface y = 2 + 0.1 cos(2 pi x), At 0.5, Re 3000, g = -e_y;
+             boundaries as bubble2d (Riemann top at P 100)
 Phase 1 is air (gamma 1.4, P_inf 0), phase 2 water-like (gamma 4.4,
 P_inf 0.6), except in bubble2d where phase 1 is the heavy surrounding
 liquid; alpha is the volume fraction of phase 1 and psi increases towards
@@ -36,7 +39,7 @@ import math
 import numpy as np
 
 ORDER = 3
-NAMES = ("drop1d", "drop2d", "shock2d", "rt3d", "adjoint2d", "waterair2d", "bubble2d")
+NAMES = ("drop1d", "drop2d", "shock2d", "rt3d", "adjoint2d", "waterair2d", "bubble2d", "rt2d")
 FULL_ELEMS = {
     "drop1d": (100,),
     "drop2d": (128, 128),
@@ -45,6 +48,7 @@ FULL_ELEMS = {
     "adjoint2d": (128, 128),
     "waterair2d": (24, 24),
     "bubble2d": (20, 40),
+    "rt2d": (20, 80),
 }
 
 
@@ -78,7 +82,7 @@ def config(name, n_elem=None):
 
     ``n_elem`` overrides the element counts (reduced sizes for parity tests);
     eps follows the rule eps = h / (2 (p+1)) of the configuration's own grid
-    (waterair2d: eps = h / 2).
+    (waterair2d, bubble2d, rt2d: eps = h / 2).
     """
     if name not in NAMES:
         raise KeyError(name)
@@ -122,6 +126,16 @@ def config(name, n_elem=None):
         base.update(gamma=(4.4, 1.4), pinf=(6.0e4, 0.0), rho0=(1000.0, 100.0),
                     mu=(10.0, 1.0), sigma=24.5, g=(0.0, -0.98, 0.0))
         cfg["bc_state"] = {(1, 1): [cfg["p_top"]]}
+    elif name == "rt2d":
+        # At = (rho_h - rho_l)/(rho_h + rho_l) = 0.5, Re = rho_h d^(3/2) |g|^(1/2)
+        # / mu = 3000 with d = 1, |g| = 1; light phase 1 below, heavy phase 2
+        # above; ideal gases at a Mach number near 0.1
+        cfg.update(dim=2, lo=(0.0, 0.0), hi=(1.0, 4.0),
+                   bc=[("slip_wall", "slip_wall"), ("no_slip", "riemann")],
+                   t_end=3.0 * math.sqrt(2.0), steps=200, p_top=100.0)
+        base.update(gamma=(1.4, 1.4), pinf=(0.0, 0.0), rho0=(1.0, 3.0),
+                    mu=(1e-3, 1e-3), g=(0.0, -1.0, 0.0))
+        cfg["bc_state"] = {(1, 1): [cfg["p_top"]]}
     elif name == "rt3d":
         cfg.update(dim=3, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
                    bc=[("periodic", "periodic")] * 2 + [("slip_wall", "slip_wall")],
@@ -132,8 +146,11 @@ def config(name, n_elem=None):
         raise ValueError("n_elem has the wrong length")
     h = min((cfg["hi"][k] - cfg["lo"][k]) / n_elem[k] for k in range(d))
     # eps: half a nodal spacing; the water droplet in air (air density 1e-3,
-    # where an overshoot of alpha by 1e-3 empties the air) two nodal spacings
-    base["eps"] = (0.5 * h) if name == "waterair2d" else 0.5 * h / (p + 1)
+    # where an overshoot of alpha by 1e-3 empties the air) and the two
+    # wall-bounded cases (bubble2d, rt2d: their interfaces stay in bounds only
+    # so) h / 2
+    wide = name in ("waterair2d", "bubble2d", "rt2d")
+    base["eps"] = (0.5 * h) if wide else 0.5 * h / (p + 1)
     cfg["params"] = base
     cfg.setdefault("bc_prim", {})
     cfg.setdefault("bc_state", {})
@@ -217,6 +234,15 @@ def primitive_fields(cfg, coords, variant=None):
         inside = 1.0 - _sigmoid(psi / eps)
         P = (cfg["p_top"] + r1 * (-prm["g"][1]) * (cfg["hi"][1] - X[1])
              + prm["sigma"] / cfg["radius"] * inside)
+    elif name == "rt2d":
+        x, y = X[0], X[1]
+        eta = 2.0 + 0.1 * np.cos(2.0 * math.pi * x)
+        psi = eta - y
+        top = cfg["hi"][1]
+        # hydrostatic column for g = -e_y under P_top:
+        # P = P_top + int_y^top rho dy' with rho = rho2 + (rho1 - rho2) alpha
+        P = (cfg["p_top"] + r2 * (top - y)
+             + (r1 - r2) * eps * (_softplus((eta - y) / eps) - _softplus((eta - top) / eps)))
     elif name == "rt3d":
         x, y, z = X[0], X[1], X[2]
         eta = (0.5 + 0.02 * np.cos(2 * math.pi * x) * np.cos(2 * math.pi * y)
