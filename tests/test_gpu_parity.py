@@ -28,8 +28,8 @@ def _dg():
     return dg2p
 
 
-def gpu_case(name, n_elem=None, variant=None, bc=None, **over):
-    cfg, om, prm, U0 = oracle_setup(name, n_elem=n_elem, variant=variant, bc=bc, **over)
+def gpu_case(name, n_elem=None, variant=None, bc=None, bc_state=None, **over):
+    cfg, om, prm, U0 = oracle_setup(name, n_elem=n_elem, variant=variant, bc=bc, bc_state=bc_state, **over)
     dg = _dg()
     P = dg.make_params({**cfg["params"], **over})
     mesh = dg.mesh_from_config(dict(cfg, params={**cfg["params"], **over}), P)
@@ -80,6 +80,31 @@ def test_rhs_parity(name, ne, variant):
     rate = oracle.max_rate(U0, om, prm)
     errs = res_errors(Rg, Ro, U0, rate, prm, om.d)
     print(name, ne, variant, ["%.1e" % e for e in errs])
+    assert max(errs) <= TOL, errs
+
+
+WALL_KINDS = [
+    # 3D: no-slip in x, Riemann top (the column's own top pressure) over a no-slip bottom in z
+    ("rt3d", (2, 3, 3), [("no_slip", "no_slip"), ("periodic", "periodic"), ("no_slip", "riemann")],
+     {(2, 1): [1.0]}),
+    # 1D: Riemann inflow side (u = 1 enters) against a no-slip wall
+    ("drop1d", (13,), [("riemann", "no_slip")], {(0, 0): [1.0]}),
+    # 1D: pressure below the state's at the Riemann side (outflow expansion)
+    ("drop1d", (9,), [("no_slip", "riemann")], {(0, 1): [0.8]}),
+    # 2D periodic droplet boxed by no-slip walls (every face of the corner elements a wall)
+    ("drop2d", (5, 4), [("no_slip", "no_slip"), ("no_slip", "no_slip")], None),
+]
+
+
+@pytest.mark.parametrize("name,ne,bc,bcs", WALL_KINDS)
+def test_rhs_parity_wall_kinds(name, ne, bc, bcs):
+    """The no-slip and Riemann-invariant ghosts in 1D and 3D (the loop form of
+    the face pass) and on every side of a 2D box."""
+    cfg, om, prm, U0, mesh, P = gpu_case(name, ne, bc=bc, bc_state=bcs)
+    Ro = oracle.rhs(U0, om, prm)
+    Rg = _dg().rhs(mesh, P, U0.cuda().contiguous()).cpu()
+    errs = res_errors(Rg, Ro, U0, oracle.max_rate(U0, om, prm), prm, om.d)
+    print(name, ne, bc, ["%.1e" % e for e in errs])
     assert max(errs) <= TOL, errs
 
 
