@@ -327,6 +327,15 @@ def monitors(mesh, params, U, p_ref=0.0, u_ref=None, stream=None, sync=True):
     return decode_monitors(buf, mesh.nf)
 
 
+def require_physical(mon, what="state"):
+    """Raise Dg2pError(DG2P_ENONPHYS) when decoded monitors count
+    non-physical nodes (partial densities summing to <= 0, (1+xi) P + Pi <= 0,
+    or a NaN / Inf); returns the monitors otherwise."""
+    if mon["nonphys"] > 0:
+        raise Dg2pError(ENONPHYS, f"{what}: {mon['nonphys']} non-physical nodes")
+    return mon
+
+
 def timing_enable(on=True):
     """Bracket every library kernel launch with hipEvents (benchmarks only)."""
     _check(_lib.dg2p_timing_enable(1 if on else 0), "dg2p_timing_enable")

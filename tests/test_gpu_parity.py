@@ -507,3 +507,44 @@ def test_rising_bubble_rises():
     y1, v1 = centre(U)
     print("t", float(t.cpu()), "y_c", y0, "->", y1, "v_c", v0, "->", v1)
     assert y1 > y0 + 0.02 and v1 > 0.05
+
+
+def test_checkpoint_resume_is_bitwise(tmp_path):
+    """40 steps of dg2p_advance against 20 steps, a checkpoint written and read
+    back, and 20 more: the same state and time, bit for bit."""
+    from paper_2306_05002_amd import checkpoint
+    cfg, om, prm, U0, mesh, P = gpu_case("rt3d", (3, 3, 4))
+    dg = _dg()
+    A = U0.cuda().contiguous()
+    ta = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dg.advance(mesh, P, A, 40, cfl=0.1, t=ta)
+    B = U0.cuda().contiguous()
+    tb = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dg.advance(mesh, P, B, 20, cfl=0.1, t=tb)
+    path = tmp_path / "run.npz"
+    checkpoint.save(path, B, tb, 20, cfg["params"], {"n_elem": list(cfg["n_elem"]), "bc": cfg["bc"]})
+    del B, tb
+    ck = checkpoint.load(path)
+    assert ck["step"] == 20 and ck["params"] == json_round(cfg["params"])
+    P2 = dg.make_params(ck["params"])
+    dg.advance(mesh, P2, ck["U"], 20, cfl=0.1, t=ck["t"])
+    assert torch.equal(ck["U"], A)
+    assert torch.equal(ck["t"], ta)
+
+
+def json_round(d):
+    import json
+    return json.loads(json.dumps(d, sort_keys=True))
+
+
+def test_require_physical_raises_on_injected_nodes():
+    """The sync helper turns counted non-physical nodes into DG2P_ENONPHYS."""
+    cfg, om, prm, U0, mesh, P = gpu_case("drop2d", (4, 4))
+    dg = _dg()
+    good = dg.monitors(mesh, P, U0.cuda().contiguous())
+    assert dg.require_physical(good) is good
+    U = U0.clone()
+    U[0, 2, 3] = float("inf")
+    with pytest.raises(dg.Dg2pError) as ei:
+        dg.require_physical(dg.monitors(mesh, P, U.cuda().contiguous()))
+    assert ei.value.status == dg.ENONPHYS
