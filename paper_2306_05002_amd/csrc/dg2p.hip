@@ -168,13 +168,18 @@ struct TimedLaunch {
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 bool viscous(const dg2p_params* p) { return p->mu[0] != 0.0 || p->mu[1] != 0.0; }
-// boundary kinds whose ghost needs the side's bc_state (compiled in only
-// where a mesh has them)
-bool has_dirichlet(const dg2p_mesh_s* m) {
+// boundary code the stage kernels compile in: 0 = none (periodic mesh), 1 =
+// ghosts built from the interior trace (walls, extrapolation), 2 = also those
+// that read the side's bc_state (Dirichlet, Riemann)
+int bc_class(const dg2p_mesh_s* m) {
+  int c = 0;
   for (int k = 0; k < m->dim; ++k)
-    for (int s = 0; s < 2; ++s)
-      if (m->desc.bc[k][s] == DG2P_BC_DIRICHLET || m->desc.bc[k][s] == DG2P_BC_RIEMANN) return true;
-  return false;
+    for (int s = 0; s < 2; ++s) {
+      const int b = m->desc.bc[k][s];
+      if (b == DG2P_BC_DIRICHLET || b == DG2P_BC_RIEMANN) c = 2;
+      else if (b != DG2P_BC_PERIODIC && c < 1) c = 1;
+    }
+  return c;
 }
 
 size_t g_bytes(const dg2p_mesh_s* m, const dg2p_params* p) {
@@ -272,46 +277,51 @@ void launch_ingredients(int prec, const KArgs& A, const double* U, double* G, do
   else launch_ingredients_p<DIM, VISC, 0>(A, U, G, rec, s);
 }
 
-template <int DIM, bool VISC, bool CSF, bool DIRI, int PR>
+template <int DIM, bool VISC, bool CSF, int BCK, int PR>
 void launch_stage_p(int mode, int epi, const KArgs& A, const StageIO& io, hipStream_t s) {
   TimedLaunch t(DG2P_K_STAGE, s);
   const dim3 g = elem_grid(A), b(BLOCK);
   if (mode == 0)
-    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 0, 0, PR>), g, b, 0, s, A, io);
+    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, BCK, 0, 0, PR>), g, b, 0, s, A, io);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 1, 1, PR>), g, b, 0, s, A, io);
+    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, BCK, 1, 1, PR>), g, b, 0, s, A, io);
   else if (epi == 1)
-    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 2, 1, PR>), g, b, 0, s, A, io);
+    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, BCK, 2, 1, PR>), g, b, 0, s, A, io);
   else if (epi == 2)
-    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 2, 2, PR>), g, b, 0, s, A, io);
+    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, BCK, 2, 2, PR>), g, b, 0, s, A, io);
   else if (epi == 3)
-    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 2, 3, PR>), g, b, 0, s, A, io);
+    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, BCK, 2, 3, PR>), g, b, 0, s, A, io);
   else
-    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, DIRI, 2, 0, PR>), g, b, 0, s, A, io);
+    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, BCK, 2, 0, PR>), g, b, 0, s, A, io);
 }
-template <int DIM, bool VISC, bool CSF, bool DIRI>
+template <int DIM, bool VISC, bool CSF, int BCK>
 void launch_stage_t(int prec, int mode, int epi, const KArgs& A, const StageIO& io, hipStream_t s) {
-  if (prec == DG2P_MIXED_FP32) launch_stage_p<DIM, VISC, CSF, DIRI, 1>(mode, epi, A, io, s);
-  else if (prec == DG2P_MIXED_BF16) launch_stage_p<DIM, VISC, CSF, DIRI, 2>(mode, epi, A, io, s);
-  else launch_stage_p<DIM, VISC, CSF, DIRI, 0>(mode, epi, A, io, s);
+  if (prec == DG2P_MIXED_FP32) launch_stage_p<DIM, VISC, CSF, BCK, 1>(mode, epi, A, io, s);
+  else if (prec == DG2P_MIXED_BF16) launch_stage_p<DIM, VISC, CSF, BCK, 2>(mode, epi, A, io, s);
+  else launch_stage_p<DIM, VISC, CSF, BCK, 0>(mode, epi, A, io, s);
+}
+
+template <int DIM, int BCK>
+void launch_stage_b(bool visc, bool csf, int pr, int mode, int epi, const KArgs& A, const StageIO& io,
+                    hipStream_t s) {
+  if (visc && csf) launch_stage_t<DIM, true, true, BCK>(pr, mode, epi, A, io, s);
+  else if (visc) launch_stage_t<DIM, true, false, BCK>(pr, mode, epi, A, io, s);
+  else if (csf) launch_stage_t<DIM, false, true, BCK>(pr, mode, epi, A, io, s);
+  else launch_stage_t<DIM, false, false, BCK>(pr, mode, epi, A, io, s);
 }
 
 template <int DIM>
 void launch_stage_d(const dg2p_mesh_s* m, const dg2p_params* p, int mode, int epi, const KArgs& A,
                     const StageIO& io, hipStream_t s) {
-  const bool visc = viscous(p), csf = p->sigma != 0.0, diri = has_dirichlet(m);
+  const bool visc = viscous(p), csf = p->sigma != 0.0;
+  const int bck = bc_class(m);
   const int pr = p->precision;
-  if (diri) {
-    if (visc && csf) launch_stage_t<DIM, true, true, true>(pr, mode, epi, A, io, s);
-    else if (visc) launch_stage_t<DIM, true, false, true>(pr, mode, epi, A, io, s);
-    else if (csf) launch_stage_t<DIM, false, true, true>(pr, mode, epi, A, io, s);
-    else launch_stage_t<DIM, false, false, true>(pr, mode, epi, A, io, s);
-  } else {
-    if (visc && csf) launch_stage_t<DIM, true, true, false>(pr, mode, epi, A, io, s);
-    else if (visc) launch_stage_t<DIM, true, false, false>(pr, mode, epi, A, io, s);
-    else if (csf) launch_stage_t<DIM, false, true, false>(pr, mode, epi, A, io, s);
-    else launch_stage_t<DIM, false, false, false>(pr, mode, epi, A, io, s);
-  }
+  if (bck == 2)
+    launch_stage_b<DIM, 2>(visc, csf, pr, mode, epi, A, io, s);
+  else if (bck == 1)
+    launch_stage_b<DIM, 1>(visc, csf, pr, mode, epi, A, io, s);
+  else
+    launch_stage_b<DIM, 0>(visc, csf, pr, mode, epi, A, io, s);
 }
 
 void launch_stage(const dg2p_mesh_s* m, const dg2p_params* p, int mode, int epi, const KArgs& A,

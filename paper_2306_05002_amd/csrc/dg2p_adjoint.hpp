@@ -310,10 +310,8 @@ __global__ __launch_bounds__(BLOCK) void k_vjp_local(KArgs A, VjpIO io) {
     const int akk = ak[k];
     const bool isface = (akk == 0) || (akk == 3);
     // cotangent of the face values spread by the symmetric term
-    const double wlo = sel4(akk, GLL.D[0][0] / GLL.w[0], GLL.D[0][1] / GLL.w[1], GLL.D[0][2] / GLL.w[2],
-                            GLL.D[0][3] / GLL.w[3]) * A.hJ2inv[k];
-    const double whi = sel4(akk, GLL.D[3][0] / GLL.w[0], GLL.D[3][1] / GLL.w[1], GLL.D[3][2] / GLL.w[2],
-                            GLL.D[3][3] / GLL.w[3]) * A.hJ2inv[k];
+    const double wlo = kCoef.sp[0][akk] * A.hJ2inv[k];
+    const double whi = kCoef.sp[1][akk] * A.hJ2inv[k];
     double symb[NC + 1];
 #pragma unroll
     for (int i = 0; i <= NC; ++i) {

@@ -106,6 +106,31 @@ constexpr double CX(int a, int r) { return GLL.D[a][(a + r) & 3]; }
 constexpr double CY(int a, int r) { return GLL.D[a][(a - r) & 3]; }
 constexpr double CZ(int a, int r) { return GLL.D[a][a ^ r]; }
 
+// The same coefficients as a table read with the lane's own a_k (a load from
+// cached constant memory instead of a selection among compile-time
+// constants, which compiles to branches): c[k][a][r] = the axis-k rotation
+// r coefficient of a node at position a; sp[0][a] = D[0][a] / w_a and
+// sp[1][a] = D[3][a] / w_a, the SIPG spread weights of the line's low and
+// high ends.
+struct CoefTab {
+  double c[3][4][4];
+  double sp[2][4];
+};
+constexpr CoefTab make_coef_tab() {
+  CoefTab t{};
+  for (int a = 0; a < 4; ++a) {
+    for (int r = 0; r < 4; ++r) {
+      t.c[0][a][r] = CX(a, r);
+      t.c[1][a][r] = CY(a, r);
+      t.c[2][a][r] = CZ(a, r);
+    }
+    t.sp[0][a] = GLL.D[0][a] / GLL.w[a];
+    t.sp[1][a] = GLL.D[3][a] / GLL.w[a];
+  }
+  return t;
+}
+__constant__ CoefTab kCoef = make_coef_tab();
+
 struct KArgs {
   long long E;
   long long nblocks;    // logical workgroups of the element passes
@@ -197,10 +222,9 @@ template <int DIM>
 __device__ __forceinline__ void lane_coeffs(const KArgs& A, const int* ak, LaneD<DIM>& L) {
   (void)A;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    L.c[0][r] = sel4(ak[0], CX(0, r), CX(1, r), CX(2, r), CX(3, r));
-    if constexpr (DIM > 1) L.c[1][r] = sel4(ak[1], CY(0, r), CY(1, r), CY(2, r), CY(3, r));
-    if constexpr (DIM > 2) L.c[2][r] = sel4(ak[2], CZ(0, r), CZ(1, r), CZ(2, r), CZ(3, r));
+  for (int k = 0; k < DIM; ++k) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) L.c[k][r] = kCoef.c[k][ak[k]][r];
   }
 }
 
@@ -262,16 +286,11 @@ struct LaneF {
 template <int DIM, int PR>
 __device__ __forceinline__ void lane_coeffs_f(const int* ak, LaneF<DIM>& L) {
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    float x = (float)sel4(ak[0], CX(0, r), CX(1, r), CX(2, r), CX(3, r));
-    L.c[0][r] = PR == 2 ? bf16_round(x) : x;
-    if constexpr (DIM > 1) {
-      float y = (float)sel4(ak[1], CY(0, r), CY(1, r), CY(2, r), CY(3, r));
-      L.c[1][r] = PR == 2 ? bf16_round(y) : y;
-    }
-    if constexpr (DIM > 2) {
-      float z = (float)sel4(ak[2], CZ(0, r), CZ(1, r), CZ(2, r), CZ(3, r));
-      L.c[2][r] = PR == 2 ? bf16_round(z) : z;
+  for (int k = 0; k < DIM; ++k) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float x = (float)kCoef.c[k][ak[k]][r];
+      L.c[k][r] = PR == 2 ? bf16_round(x) : x;
     }
   }
 }
@@ -346,7 +365,12 @@ __device__ __forceinline__ double line_end(double f, int ak_k, bool high) {
 template <int DIM>
 __device__ __forceinline__ void closure(const KArgs& A, const double* q, Prim& p) {
   p.rho = q[0] + q[1];
-  const double ri = 1.0 / p.rho;
+  const double al = q[3 + DIM];
+  const double xi = al * A.xi1 + (1.0 - al) * A.xi2;
+  const double pi = al * A.pi1 + (1.0 - al) * A.pi2;
+  // one division: 1/rho = xi inv and 1/xi = rho inv with inv = 1/(xi rho)
+  const double inv = 1.0 / (xi * p.rho);
+  const double ri = xi * inv;
   double k2 = 0.0;
 #pragma unroll
   for (int j = 0; j < DIM; ++j) {
@@ -354,12 +378,9 @@ __device__ __forceinline__ void closure(const KArgs& A, const double* q, Prim& p
     k2 = fma(p.u[j], p.u[j], k2);
   }
   p.kin = 0.5 * k2;
-  const double al = q[3 + DIM];
   const double rhoe = q[2 + DIM] - p.rho * p.kin;
-  const double xi = al * A.xi1 + (1.0 - al) * A.xi2;
-  const double pi = al * A.pi1 + (1.0 - al) * A.pi2;
-  p.P = (rhoe - pi) / xi;
-  p.c = sqrt(((1.0 + xi) * p.P + pi) / (xi * p.rho));
+  p.P = (rhoe - pi) * (p.rho * inv);
+  p.c = sqrt(((1.0 + xi) * p.P + pi) * inv);
   p.sE = A.gh1 * (p.P + A.pinf1) - A.gh2 * (p.P + A.pinf2);
 }
 
@@ -774,7 +795,7 @@ __device__ __forceinline__ void face_load(const KArgs& A, const double* __restri
 // Dirichlet ghosts, d_kd alpha and n_kd (gA_k, nh_k).  The neighbour's trace
 // is qn with its ingredients an (a.e_kd) and tn (traction), as loaded by
 // face_load, or is built as the boundary ghost when bnd.
-template <int DIM, bool VISC, bool DIRI>
+template <int DIM, bool VISC, int BCK>
 __device__ __forceinline__ void face_flux(const KArgs& A, int kd, int side, bool bnd, const double* qn, double an,
                                           const double* tn, const double* q, const Prim& pr, double a_k, double mu,
                                           const double* Sk, double gA_k, double nh_k, double* Rc, double* symv) {
@@ -784,7 +805,7 @@ __device__ __forceinline__ void face_flux(const KArgs& A, int kd, int side, bool
   double qe[NF];
   double aek;
   double tek[DIM];
-  if (!bnd) {
+  if (BCK == 0 || !bnd) {
 #pragma unroll
     for (int f = 0; f < NF; ++f) qe[f] = qn[f];
     aek = an;
@@ -816,7 +837,7 @@ __device__ __forceinline__ void face_flux(const KArgs& A, int kd, int side, bool
           if (slip && j != kd) tek[j] = -tek[j];
       }
     }
-    if constexpr (DIRI) {
+    if constexpr (BCK == 2) {
       if (kind == DG2P_BC_RIEMANN) {
         // far field at rest with pressure P_b: invariants u.n +- 2 xi c of the
         // mixture stiffened gas at the interior composition and density
@@ -916,10 +937,8 @@ __device__ __forceinline__ void face_flux(const KArgs& A, int kd, int side, bool
 template <int K, int DIM>
 __device__ __forceinline__ void spread_sym(const KArgs& A, int akk, const double* symv, double* R) {
   constexpr int NC = DIM + 3;
-  const double wlo = sel4(akk, GLL.D[0][0] / GLL.w[0], GLL.D[0][1] / GLL.w[1], GLL.D[0][2] / GLL.w[2],
-                          GLL.D[0][3] / GLL.w[3]) * A.hJ2inv[K];
-  const double whi = sel4(akk, GLL.D[3][0] / GLL.w[0], GLL.D[3][1] / GLL.w[1], GLL.D[3][2] / GLL.w[2],
-                          GLL.D[3][3] / GLL.w[3]) * A.hJ2inv[K];
+  const double wlo = kCoef.sp[0][akk] * A.hJ2inv[K];
+  const double whi = kCoef.sp[1][akk] * A.hJ2inv[K];
 #pragma unroll
   for (int i = 0; i <= NC; ++i) {
     const double lo = line_end<K>(symv[i], akk, false);
@@ -933,8 +952,10 @@ __device__ __forceinline__ void spread_sym(const KArgs& A, int akk, const double
 // Stage pass: residual of each element (volume terms, sources, all faces, SIPG
 // symmetric term), then MODE 0: store R; MODE 1: U_out = U_s + dt R;
 // MODE 2: U_out = rk_a U_n + rk_b (U_s + dt R).  Epilogue on U_out: EPI = 1
-// face ingredients into Gout, EPI = 2 also the reduction records.
-template <int DIM, bool VISC, bool CSF, bool DIRI, int MODE, int EPI, int PR>
+// face ingredients into Gout, EPI = 2 also the reduction records.  BCK: 0 =
+// periodic mesh (no ghost code), 1 = walls / extrapolation, 2 = also kinds
+// that read the side's bc_state (Dirichlet, Riemann).
+template <int DIM, bool VISC, bool CSF, int BCK, int MODE, int EPI, int PR>
 __global__ __launch_bounds__(BLOCK, min_waves<DIM>()) void k_stage(KArgs A, StageIO io) {
   constexpr int NN = 1 << (2 * DIM);
   constexpr int EPW = 64 / NN;
@@ -977,7 +998,7 @@ __global__ __launch_bounds__(BLOCK, min_waves<DIM>()) void k_stage(KArgs A, Stag
     long long c = ec[k] + (side ? 1 : -1);
     bool bnd = false;
     if (c < 0 || c >= A.N[k]) {
-      if (A.bc[k][side] == DG2P_BC_PERIODIC)
+      if (BCK == 0 || A.bc[k][side] == DG2P_BC_PERIODIC)
         c = (c < 0) ? A.N[k] - 1 : 0;
       else
         bnd = true;
@@ -1005,7 +1026,7 @@ __global__ __launch_bounds__(BLOCK, min_waves<DIM>()) void k_stage(KArgs A, Stag
     } else {
       long long c = ec[1] + (jside ? 1 : -1);
       if (c < 0 || c >= A.N[1]) {
-        if ((jside ? A.bc[1][1] : A.bc[1][0]) == DG2P_BC_PERIODIC)
+        if (BCK == 0 || (jside ? A.bc[1][1] : A.bc[1][0]) == DG2P_BC_PERIODIC)
           c = (c < 0) ? A.N[1] - 1 : 0;
         else
           jbnd = true;
@@ -1123,13 +1144,13 @@ __global__ __launch_bounds__(BLOCK, min_waves<DIM>()) void k_stage(KArgs A, Stag
       Sk[1] = xjob ? g.S[1][0] : s11;
     }
     double gAk = 0.0, nhk = 0.0;
-    if constexpr (DIRI) {
+    if constexpr (BCK == 2) {
       const double ga1 = __shfl(g.gA[1], olane), nh1 = __shfl(g.nh[1], olane);
       gAk = xjob ? g.gA[0] : ga1;
       nhk = xjob ? g.nh[0] : nh1;
     }
     double Rc[NF], sv[NC + 1];
-    face_flux<2, VISC, DIRI>(A, xjob ? 0 : 1, jside, jbnd, qn, an, tn, qo, po, ao, mu, Sk, gAk, nhk, Rc, sv);
+    face_flux<2, VISC, BCK>(A, xjob ? 0 : 1, jside, jbnd, qn, an, tn, qo, po, ao, mu, Sk, gAk, nhk, Rc, sv);
     double symv[NC + 1];
 #pragma unroll
     for (int i = 0; i <= NC; ++i) symv[i] = xjob ? sv[i] : 0.0;
@@ -1168,14 +1189,14 @@ __global__ __launch_bounds__(BLOCK, min_waves<DIM>()) void k_stage(KArgs A, Stag
           else Sk[j] = 0.0;
         }
         double gAk = 0.0, nhk = 0.0;
-        if constexpr (DIRI) {
+        if constexpr (BCK == 2) {
           gAk = g.gA[k];
           nhk = g.nh[k];
         }
         double qk[NF], ank, tk[DIM];
         face_load<DIM, VISC>(A, Us, Gin, k, akk == 3, enb[k], node + (3 - 2 * akk) * S, face_index(node, k), qk,
                              ank, tk);
-        face_flux<DIM, VISC, DIRI>(A, k, akk == 3, bndk[k], qk, ank, tk, q, pr, g.a[k], g.mu, Sk, gAk, nhk, Rc, symv);
+        face_flux<DIM, VISC, BCK>(A, k, akk == 3, bndk[k], qk, ank, tk, q, pr, g.a[k], g.mu, Sk, gAk, nhk, Rc, symv);
 #pragma unroll
         for (int f = 0; f < NF; ++f) R[f] += Rc[f];
       }

@@ -174,10 +174,8 @@ __global__ __launch_bounds__(BLOCK) void k_kin_stage(KArgs A, KinIO io) {
       symv = sm * A.GammaEps * jump;
     }
     // SIPG symmetric term along the normal line through each face node
-    const double wlo = sel4(akk, GLL.D[0][0] / GLL.w[0], GLL.D[0][1] / GLL.w[1], GLL.D[0][2] / GLL.w[2],
-                            GLL.D[0][3] / GLL.w[3]) * A.hJ2inv[k];
-    const double whi = sel4(akk, GLL.D[3][0] / GLL.w[0], GLL.D[3][1] / GLL.w[1], GLL.D[3][2] / GLL.w[2],
-                            GLL.D[3][3] / GLL.w[3]) * A.hJ2inv[k];
+    const double wlo = kCoef.sp[0][akk] * A.hJ2inv[k];
+    const double whi = kCoef.sp[1][akk] * A.hJ2inv[k];
     double lo, hi;
     if (k == 0) {
       lo = line_end<0>(symv, akk, false);
@@ -435,10 +433,8 @@ __global__ __launch_bounds__(BLOCK) void k_reinit_stage(KArgs A, ReinitIO io) {
       R += A.lift[k] * (ahat - amI);
       symv = sm * A.GammaEps * jump;
     }
-    const double wlo = sel4(akk, GLL.D[0][0] / GLL.w[0], GLL.D[0][1] / GLL.w[1], GLL.D[0][2] / GLL.w[2],
-                            GLL.D[0][3] / GLL.w[3]) * A.hJ2inv[k];
-    const double whi = sel4(akk, GLL.D[3][0] / GLL.w[0], GLL.D[3][1] / GLL.w[1], GLL.D[3][2] / GLL.w[2],
-                            GLL.D[3][3] / GLL.w[3]) * A.hJ2inv[k];
+    const double wlo = kCoef.sp[0][akk] * A.hJ2inv[k];
+    const double whi = kCoef.sp[1][akk] * A.hJ2inv[k];
     double lo, hi;
     if (k == 0) {
       lo = line_end<0>(symv, akk, false);
