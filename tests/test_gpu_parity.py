@@ -436,7 +436,7 @@ def test_vjp_rejects_unsupported():
     assert ei.value.status == dg.EUNSUPPORTED
 
 
-FULL = ["drop2d", "shock2d", "adjoint2d", "rt3d", "bubble2d"]
+FULL = ["drop2d", "shock2d", "adjoint2d", "rt3d", "bubble2d", "rt2d", "waterair2d"]
 
 
 def _sample_elements(cfg, n=48, seed=0):
