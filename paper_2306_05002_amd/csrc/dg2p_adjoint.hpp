@@ -32,13 +32,28 @@ constexpr double CXT(int b, int r) { return GLL.D[(b + r) & 3][b]; }
 constexpr double CYT(int b, int r) { return GLL.D[(b - r) & 3][b]; }
 constexpr double CZT(int b, int r) { return GLL.D[b ^ r][b]; }
 
+// the same as a table read with the lane's own a_k (see CoefTab)
+struct CoefTabT {
+  double c[3][4][4];
+};
+constexpr CoefTabT make_coef_tab_t() {
+  CoefTabT t{};
+  for (int b = 0; b < 4; ++b)
+    for (int r = 0; r < 4; ++r) {
+      t.c[0][b][r] = CXT(b, r);
+      t.c[1][b][r] = CYT(b, r);
+      t.c[2][b][r] = CZT(b, r);
+    }
+  return t;
+}
+__constant__ CoefTabT kCoefT = make_coef_tab_t();
+
 template <int DIM>
 __device__ __forceinline__ void lane_coeffs_T(const int* ak, LaneD<DIM>& L) {
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    L.c[0][r] = sel4(ak[0], CXT(0, r), CXT(1, r), CXT(2, r), CXT(3, r));
-    if constexpr (DIM > 1) L.c[1][r] = sel4(ak[1], CYT(0, r), CYT(1, r), CYT(2, r), CYT(3, r));
-    if constexpr (DIM > 2) L.c[2][r] = sel4(ak[2], CZT(0, r), CZT(1, r), CZT(2, r), CZT(3, r));
+  for (int k = 0; k < DIM; ++k) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) L.c[k][r] = kCoefT.c[k][ak[k]][r];
   }
 }
 

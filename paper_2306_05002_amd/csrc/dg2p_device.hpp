@@ -111,10 +111,11 @@ constexpr double CZ(int a, int r) { return GLL.D[a][a ^ r]; }
 // constants, which compiles to branches): c[k][a][r] = the axis-k rotation
 // r coefficient of a node at position a; sp[0][a] = D[0][a] / w_a and
 // sp[1][a] = D[3][a] / w_a, the SIPG spread weights of the line's low and
-// high ends.
+// high ends; w[a] the GLL weight.
 struct CoefTab {
   double c[3][4][4];
   double sp[2][4];
+  double w[4];
 };
 constexpr CoefTab make_coef_tab() {
   CoefTab t{};
@@ -126,6 +127,7 @@ constexpr CoefTab make_coef_tab() {
     }
     t.sp[0][a] = GLL.D[0][a] / GLL.w[a];
     t.sp[1][a] = GLL.D[3][a] / GLL.w[a];
+    t.w[a] = GLL.w[a];
   }
   return t;
 }
@@ -183,10 +185,6 @@ struct StageIO {
 struct Prim {
   double rho, u[3], kin, P, c, sE;  // sE = rho1 H1 - rho2 H2
 };
-
-__device__ __forceinline__ double sel4(int a, double c0, double c1, double c2, double c3) {
-  return a == 0 ? c0 : (a == 1 ? c1 : (a == 2 ? c2 : c3));
-}
 
 // ---- cross-lane moves of a double -------------------------------------------
 template <int CTRL>
@@ -568,7 +566,7 @@ __device__ __forceinline__ void node_record(const KArgs& A, const double* q, con
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
     const int a = (node >> (2 * k)) & 3;
-    W *= sel4(a, GLL.w[0], GLL.w[1], GLL.w[2], GLL.w[3]) * A.J[k];
+    W *= kCoef.w[a] * A.J[k];
   }
   v[R_WAVE] = valid ? w : 0.0;
   v[R_NU] = valid ? nu : 0.0;

@@ -256,7 +256,7 @@ __global__ __launch_bounds__(BLOCK) void k_kin_errors(KArgs A, const double* __r
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
       const int a = (node >> (2 * k)) & 3;
-      W *= sel4(a, GLL.w[0], GLL.w[1], GLL.w[2], GLL.w[3]) * A.J[k];
+      W *= kCoef.w[a] * A.J[k];
     }
     const double d = phi[i] - phi0[i];
     v[0] = W * fabs(d);
