@@ -94,3 +94,23 @@ def test_workspace_sizes():
     g = 6 * 4 * 64 * 16 * 8          # viscous: a and tau.e_k per face node
     assert m.workspace_bytes(p, dg2p.OP_RHS) >= g
     assert m.workspace_bytes(p, dg2p.OP_RK_STEP) >= g + 2 * state
+
+
+def _header_enum(prefix):
+    src = open(os.path.join(ROOT, "include", "dg2p.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return {m.group(1).lower(): int(m.group(2)) for m in re.finditer(prefix + r"([A-Z0-9_]+)\s*=\s*(-?\d+)", src)}
+
+
+def test_binding_enums_match_header():
+    """Boundary kinds, precisions, operation codes and struct sizes of the
+    binding agree with the header."""
+    assert _header_enum("DG2P_BC_") == dg2p.BC
+    prec = {k.replace("mixed_", ""): v for k, v in _header_enum("DG2P_").items()
+            if k in ("fp64", "mixed_fp32", "mixed_bf16")}
+    assert prec == dg2p.PRECISION
+    ops = {k: v for k, v in _header_enum("DG2P_OP_").items()}
+    assert ops["rhs"] == dg2p.OP_RHS and ops["advance"] == dg2p.OP_ADVANCE
+    assert ops["kin_rhs"] == dg2p.OP_KIN_RHS and ops["kin_aux"] == dg2p.OP_KIN_AUX
+    assert ctypes.sizeof(dg2p.MeshDesc) == 4 * 2 + 4 * 3 + 8 * 6 + 4 * 6 + 4 + 8 * 48   # incl. 4 padding bytes
+    assert ctypes.sizeof(dg2p.Monitors) == 8 * 15
