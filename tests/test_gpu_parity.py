@@ -548,3 +548,54 @@ def test_require_physical_raises_on_injected_nodes():
     with pytest.raises(dg.Dg2pError) as ei:
         dg.require_physical(dg.monitors(mesh, P, U.cuda().contiguous()))
     assert ei.value.status == dg.ENONPHYS
+
+
+def test_residual_beyond_32bit_offsets():
+    """A 2D droplet grid of 4400 x 4400 quads (7 x 19.36 M x 16 = 2.17e9 state
+    entries, past 2^31): the library's residual on every element against the
+    oracle on sampled elements.  The state is built on the GPU (the droplet
+    fields of the benchmark workload with this grid's interface width); the
+    oracle's copy holds only the sampled elements and their neighbours."""
+    dg = _dg()
+    N = 4400
+    cfg = workloads.config("drop2d", n_elem=(N, N))
+    prm = oracle.Params(**cfg["params"])
+    P = dg.make_params(cfg["params"])
+    mesh = dg.mesh_from_config(cfg, P)
+    E, nn, nf = mesh.E, mesh.nn, mesh.nf
+    assert nf * E * nn > 2 ** 31
+    ref = torch.tensor(dg.Mesh(2, (1, 1), (0, 0), (1, 1)).node_coords()[:, 0, :], device="cuda")  # nodes on [0,1]^2
+    h = 1.0 / N
+    e = torch.arange(E, device="cuda")
+    x = ((e % N).to(torch.float64)[:, None] + ref[0][None, :]) * h
+    y = ((e // N).to(torch.float64)[:, None] + ref[1][None, :]) * h
+    psi = torch.sqrt((x - 0.5) ** 2 + (y - 0.5) ** 2) - 0.15
+    del x, y, e
+    alpha = torch.sigmoid(psi / cfg["params"]["eps"])
+    one = torch.ones_like(psi)
+    prim = torch.stack([alpha, psi, prm.rho0[0] * one, prm.rho0[1] * one, one, 0.5 * one, one])
+    del alpha, psi, one
+    U = dg.prim_to_cons(mesh, P, prim)
+    del prim
+    torch.cuda.empty_cache()
+    R = dg.rhs(mesh, P, U)
+    dt = float(dg.max_dt(mesh, P, U).cpu())
+    om = oracle.OracleMesh(2, 3, (N, N), cfg["lo"], cfg["hi"], cfg["bc"])
+    el = _sample_elements(cfg, n=32, seed=1)
+    # plus two elements on the droplet rim (r = 0.15 around (0.5, 0.5))
+    el = torch.cat([el, torch.tensor([2200 * N + 2860, 2860 * N + 2200], dtype=torch.long)])
+    need = [el]
+    for k in range(2):
+        for side in (0, 1):
+            need.append(om.neighbour(el, k, side)[0])
+    need = torch.unique(torch.cat(need))
+    Uc = torch.empty((nf, E, nn), dtype=torch.float64)        # pages touched only where filled
+    Uc[:, need] = U[:, need.cuda()].cpu()
+    Ro = oracle.rhs(Uc, om, prm, elems=el)
+    Rs = R[:, el.cuda()].cpu()
+    rate = 0.1 / dt
+    errs = res_errors(Rs, Ro, Uc[:, el], rate, prm, 2)
+    print("4400^2", ["%.1e" % v for v in errs])
+    assert max(errs) <= TOL, errs
+    del U, R
+    torch.cuda.empty_cache()
