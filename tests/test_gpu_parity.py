@@ -219,6 +219,9 @@ def test_water_air_interface_equilibrium():
     print("water-air after 400 steps", m["dev_p"], m["dev_u"], m["min_alpha"], m["max_alpha"])
     assert m["nonphys"] == 0
     assert m["dev_p"] < 1e-7 and m["dev_u"] < 1e-7
+    # boundedness of the phase field (Introduction and Conclusions: it holds
+    # for suitable Gamma and eps, which this case has: eps = h/2, Gamma = |u|)
+    assert -1e-8 <= m["min_alpha"] and m["max_alpha"] <= 1.0 + 1e-8
 
 
 def test_interface_equilibrium_on_gpu():
@@ -504,6 +507,7 @@ def test_rising_bubble_rises():
         dg.advance(mesh, P, U, 200, cfl=0.1, t=t, mon=mon)
         m = dg.decode_monitors(mon, mesh.nf)
         assert m["nonphys"] == 0
+        assert -1e-8 <= m["min_alpha"] and m["max_alpha"] <= 1.0 + 1e-8     # bounded phase field
     y1, v1 = centre(U)
     print("t", float(t.cpu()), "y_c", y0, "->", y1, "v_c", v0, "->", v1)
     assert y1 > y0 + 0.02 and v1 > 0.05
