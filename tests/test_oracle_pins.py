@@ -402,3 +402,26 @@ def test_convergence_order_smooth_advection():
         errs.append(float(torch.sqrt(((U[4] - exact) ** 2 * W).sum())))
     orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
     assert orders[-1] > 3.3, (errs, orders)
+
+
+def test_equilibrium_profile_has_vanishing_interface_flux():
+    """The Allen-Cahn flux a = Gamma (eps grad alpha - alpha (1 - alpha) n)
+    vanishes for the equilibrium profile alpha = sigmoid(psi/eps) of a unit-
+    slope level set (the profile the interface relaxes to); on the grid it is
+    the nodal-derivative error, which falls at order p = 3.  A wrong sign or a
+    missing eps in either term leaves an O(1) flux."""
+    prm = oracle.Params(eps=0.05, Gamma=1.0)
+    amax = []
+    for N in (20, 40, 80):
+        om = oracle.OracleMesh(1, 3, (N,), (0.0,), (1.0,), [("periodic", "periodic")])
+        X = om.node_coords()[0]
+        psi = X - 0.5
+        al = torch.sigmoid(psi / prm.eps)
+        one = torch.ones_like(al)
+        U = oracle.prim_to_cons(al, psi, one, 10.0 * one, one[None], one, prm)
+        raw = ores._raw(U, om, prm)
+        a = ores._pointwise(raw, 1, prm)["a"][0]
+        inner = (X > 0.2) & (X < 0.8)          # away from the periodic seam of psi
+        amax.append(float(a[inner].abs().max()))
+    orders = [math.log2(amax[i] / amax[i + 1]) for i in range(2)]
+    assert amax[0] < 1e-3 and min(orders) > 2.7, (amax, orders)
