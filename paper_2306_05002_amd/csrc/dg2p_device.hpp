@@ -53,9 +53,14 @@ constexpr int BLOCK = 256;      // threads per workgroup (4 independent waves)
 #ifndef DG2P_PIN
 #define DG2P_PIN(x) asm volatile("" : "+v"(x))
 #endif
-template <int DIM>
+// the viscous quad kernel (velocity gradient and tractions on top) runs two
+// waves per SIMD: within three waves' registers it spills
+#ifndef DG2P_WAVES_2D_VISC
+#define DG2P_WAVES_2D_VISC 2
+#endif
+template <int DIM, bool VISC = false>
 constexpr int min_waves() {
-  return DIM == 1 ? DG2P_WAVES_1D : (DIM == 2 ? DG2P_WAVES_2D : DG2P_WAVES_3D);
+  return DIM == 1 ? DG2P_WAVES_1D : (DIM == 2 ? (VISC ? DG2P_WAVES_2D_VISC : DG2P_WAVES_2D) : DG2P_WAVES_3D);
 }
 constexpr int REC = 16;         // doubles per reduction record
 // record slots
@@ -954,7 +959,7 @@ __device__ __forceinline__ void spread_sym(const KArgs& A, int akk, const double
 // periodic mesh (no ghost code), 1 = walls / extrapolation, 2 = also kinds
 // that read the side's bc_state (Dirichlet, Riemann).
 template <int DIM, bool VISC, bool CSF, int BCK, int MODE, int EPI, int PR>
-__global__ __launch_bounds__(BLOCK, min_waves<DIM>()) void k_stage(KArgs A, StageIO io) {
+__global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs A, StageIO io) {
   constexpr int NN = 1 << (2 * DIM);
   constexpr int EPW = 64 / NN;
   constexpr int NF = DIM + 5;
