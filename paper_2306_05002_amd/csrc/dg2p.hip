@@ -420,6 +420,7 @@ void finalize_rate(const dg2p_mesh_s* m, const KArgs& A, const Work& w, long lon
 #define DG2P_FUSED_DT_MAX 1024
 #endif
 constexpr long long FUSED_DT_MAX = DG2P_FUSED_DT_MAX;
+static_assert(FUSED_DT_MAX <= FUSED_RATE_MAX, "a first-stage workgroup reduces at most FUSED_RATE_MAX records");
 
 bool all_periodic(const dg2p_mesh_s* m) {
   for (int k = 0; k < m->dim; ++k)

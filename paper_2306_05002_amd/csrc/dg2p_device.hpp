@@ -510,37 +510,47 @@ __device__ __forceinline__ double rate_of(double wmax, double numax, double Gamm
 }
 
 // Fused time step of a small grid: every workgroup reduces all rate records
-// (batches of independent loads; max is exact, so every workgroup obtains
-// the same value as the separate reduction kernels).
-__device__ __forceinline__ double fused_dt(const KArgs& A, const double* __restrict__ rate, const double* dt_fixed,
-                                           int dim) {
-  if (dt_fixed) return *dt_fixed;
-  constexpr int RB = 4;
+// (max is exact, so every workgroup obtains the same value as the separate
+// reduction kernels). First half, at kernel entry so that the record loads
+// overlap those of the stage input: each thread's maximum over its share of
+// the records (independent loads), then its wave's maximum, parked
+// in LDS.
+constexpr int FUSED_RATE_PER_THREAD = 4;
+constexpr long long FUSED_RATE_MAX = FUSED_RATE_PER_THREAD * BLOCK;  // records one workgroup reduces
+__device__ __forceinline__ void fused_dt_load(const KArgs& A, const double* __restrict__ rate,
+                                              double (*sh)[BLOCK / 64]) {
+  // A.nrate <= FUSED_RATE_MAX: straight-line loads (clamped to record 0,
+  // their values discarded), no loop whose latch would wait for every load
+  double vw[FUSED_RATE_PER_THREAD], vn[FUSED_RATE_PER_THREAD];
+#pragma unroll
+  for (int u = 0; u < FUSED_RATE_PER_THREAD; ++u) {
+    const long long r = threadIdx.x + u * BLOCK;
+    const long long rr = r < A.nrate ? r : 0;
+    vw[u] = rate[rr * RATE + R_WAVE];
+    vn[u] = rate[rr * RATE + R_NU];
+  }
   double w = 0.0, nu = 0.0;
-  for (long long r0 = threadIdx.x; r0 < A.nrate; r0 += RB * BLOCK) {
-    double vw[RB], vn[RB];
 #pragma unroll
-    for (int u = 0; u < RB; ++u) {
-      const long long r = r0 + u * BLOCK;
-      vw[u] = r < A.nrate ? rate[r * RATE + R_WAVE] : 0.0;
-      vn[u] = r < A.nrate ? rate[r * RATE + R_NU] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < RB; ++u) {
-      w = fmax(w, vw[u]);
-      nu = fmax(nu, vn[u]);
-    }
+  for (int u = 0; u < FUSED_RATE_PER_THREAD; ++u) {
+    const bool ok = threadIdx.x + u * BLOCK < A.nrate;
+    w = fmax(w, ok ? vw[u] : 0.0);
+    nu = fmax(nu, ok ? vn[u] : 0.0);
   }
   w = wave_max(w);
   nu = wave_max(nu);
-  __shared__ double sh[2][BLOCK / 64];
   if ((threadIdx.x & 63) == 0) {
     sh[0][threadIdx.x >> 6] = w;
     sh[1][threadIdx.x >> 6] = nu;
   }
+}
+
+// Second half, at the stage combine (the first point that needs dt, so that
+// the workgroup barrier does not hold the waves back at entry): the maxima
+// over the workgroup's waves, and dt from them.
+__device__ __forceinline__ double fused_dt_finish(const KArgs& A, double (*sh)[BLOCK / 64], int dim) {
   __syncthreads();
-  w = sh[0][0];
-  nu = sh[1][0];
+  double w = sh[0][0];
+  double nu = sh[1][0];
 #pragma unroll
   for (int i = 1; i < BLOCK / 64; ++i) {
     w = fmax(w, sh[0][i]);
@@ -981,6 +991,11 @@ __global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs
   double q[NF];
 #pragma unroll
   for (int f = 0; f < NF; ++f) q[f] = Us[(f * A.E + e) * NN + node];
+  // first stage of a small grid: the rate records of the time step
+  __shared__ double dt_lds[2][BLOCK / 64];
+  if constexpr (MODE == 1) {
+    if (io.dt_out && !io.dt_fixed) fused_dt_load(A, io.rate_in, dt_lds);
+  }
   // element multi-index and face neighbours
   long long ec[3] = {0, 0, 0};
   {
@@ -1213,7 +1228,7 @@ __global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs
   double dt_fused = 0.0;
   if constexpr (MODE == 1) {
     if (io.dt_out) {
-      dt_fused = fused_dt(A, io.rate_in, io.dt_fixed, DIM);
+      dt_fused = io.dt_fixed ? *io.dt_fixed : fused_dt_finish(A, dt_lds, DIM);
       if (blk == 0 && threadIdx.x == 0) {
         *io.dt_out = dt_fused;
         if (io.t) *io.t += dt_fused;
