@@ -1027,16 +1027,17 @@ __global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs
     enb[k] = (isface && !bnd) ? e + (c - ec[k]) * estr : e;
     bndk[k] = bnd;
   }
-  // 2D: the lane's face job (one face node of its quad, see the face pass)
-  // and the neighbour trace across it, loaded here so that the loads are in
-  // flight during the volume terms.
+  // 2D and 3D: the lane's face job (one x- or y-face node of its quad, or of
+  // its z-layer of the hexahedron, see the face pass) and the neighbour trace
+  // across it, loaded here so that the loads are in flight during the volume
+  // terms.
   bool xjob = false, jbnd = false;
   int jside = 0, onode = 0;
   double qn[NF], an = 0.0, tn[DIM];
-  if constexpr (DIM == 2) {
+  if constexpr (DIM >= 2) {
     xjob = (ak[0] == 0) || (ak[0] == 3);
     jside = xjob ? (ak[0] == 3) : (ak[0] == 2);
-    onode = xjob ? node : ak[1] + (jside ? 12 : 0);
+    onode = xjob ? node : (DIM == 3 ? (node & ~15) : 0) + ak[1] + (jside ? 12 : 0);
     long long en;
     if (xjob) {
       en = enb[0];
@@ -1052,8 +1053,8 @@ __global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs
       en = jbnd ? e : e + (c - ec[1]) * A.N[0];
     }
     const int nodee = xjob ? node + (3 - 2 * ak[0]) : onode + (jside ? -12 : 12);
-    const int fn = xjob ? (node >> 2) : ak[1];
-    face_load<2, VISC>(A, Us, io.Gin, xjob ? 0 : 1, jside, en, nodee, fn, qn, an, tn);
+    const int fn = DIM == 2 ? (xjob ? (node >> 2) : ak[1]) : (xjob ? face_index(node, 0) : face_index(onode, 1));
+    face_load<DIM, VISC>(A, Us, io.Gin, xjob ? 0 : 1, jside, en, nodee, fn, qn, an, tn);
   }
   Prim pr;
   closure<DIM>(A, q, pr);
@@ -1132,14 +1133,16 @@ __global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs
 
   // faces
   const double* __restrict__ Gin = io.Gin;
-  if constexpr (DIM == 2) {
-    // The 16 face nodes of a quad (4 faces x 4 nodes) are spread over its 16
-    // lanes, one face evaluation each: a lane with a_x in {0, 3} evaluates the
-    // x-face at its own node; a lane with a_x = 1 (2) evaluates the low (high)
-    // y-face at node (a_y, 0) ((a_y, 3)).  The owner node's trace comes from
-    // its lane and the results go back to it by lane exchanges, so no face is
-    // evaluated on half-idle lanes.
-    const int olane = (lane & 48) | onode;
+  if constexpr (DIM >= 2) {
+    // The 16 x- and y-face nodes of a quad (4 faces x 4 nodes), or of one
+    // z-layer of a hexahedron, are spread over its 16 lanes, one face
+    // evaluation each: a lane with a_x in {0, 3} evaluates the x-face at its
+    // own node; a lane with a_x = 1 (2) evaluates the low (high) y-face at
+    // node (a_y, 0, a_z) ((a_y, 3, a_z)).  The owner node's trace comes from
+    // its lane and the results go back to it by lane exchanges, so no x or y
+    // face is evaluated on half-idle lanes; the z-faces of a hexahedron
+    // follow as in the loop form.
+    const int olane = (lane & 48) | (DIM == 2 ? onode : (onode & 15));
     double qo[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) qo[f] = __shfl(q[f], olane);
@@ -1147,19 +1150,27 @@ __global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs
     po.rho = __shfl(pr.rho, olane);
     po.u[0] = __shfl(pr.u[0], olane);
     po.u[1] = __shfl(pr.u[1], olane);
-    po.u[2] = 0.0;
+    po.u[2] = DIM == 3 ? __shfl(pr.u[2], olane) : 0.0;
     po.kin = __shfl(pr.kin, olane);
     po.P = __shfl(pr.P, olane);
     po.c = __shfl(pr.c, olane);
     po.sE = __shfl(pr.sE, olane);
     const double a1 = __shfl(g.a[1], olane);
     const double ao = xjob ? g.a[0] : a1;
-    double mu = 0.0, Sk[2] = {0.0, 0.0};
-    if constexpr (VISC) {
+    double mu = 0.0, Sk[DIM] = {};
+    if constexpr (VISC && DIM == 2) {
       const double mu1 = __shfl(g.mu, olane), s01 = __shfl(g.S[0][1], olane), s11 = __shfl(g.S[1][1], olane);
       mu = xjob ? g.mu : mu1;
       Sk[0] = xjob ? g.S[0][0] : s01;
       Sk[1] = xjob ? g.S[1][0] : s11;
+    } else if constexpr (VISC) {
+      const double mu1 = __shfl(g.mu, olane);
+      mu = xjob ? g.mu : mu1;
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) {
+        const double sj1 = __shfl(g.S[j][1], olane);
+        Sk[j] = xjob ? g.S[j][0] : sj1;
+      }
     }
     double gAk = 0.0, nhk = 0.0;
     if constexpr (BCK == 2) {
@@ -1168,7 +1179,7 @@ __global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs
       nhk = xjob ? g.nh[0] : nh1;
     }
     double Rc[NF], sv[NC + 1];
-    face_flux<2, VISC, BCK>(A, xjob ? 0 : 1, jside, jbnd, qn, an, tn, qo, po, ao, mu, Sk, gAk, nhk, Rc, sv);
+    face_flux<DIM, VISC, BCK>(A, xjob ? 0 : 1, jside, jbnd, qn, an, tn, qo, po, ao, mu, Sk, gAk, nhk, Rc, sv);
     double symv[NC + 1];
 #pragma unroll
     for (int i = 0; i <= NC; ++i) symv[i] = xjob ? sv[i] : 0.0;
@@ -1176,7 +1187,7 @@ __global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs
 #pragma unroll
       for (int f = 0; f < NF; ++f) R[f] += Rc[f];
     }
-    spread_sym<0, 2>(A, ak[0], symv, R);
+    spread_sym<0, DIM>(A, ak[0], symv, R);
     // y-face results of this lane's node, from the lane that evaluated them
     const bool yown = (ak[1] == 0) || (ak[1] == 3);
     const int jl = (lane & 48) | ((ak[1] == 3 ? 2 : 1) + 4 * ak[0]);
@@ -1190,10 +1201,13 @@ __global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs
       const double v = __shfl(sv[i], jl);
       symv[i] = yown ? v : 0.0;
     }
-    spread_sym<1, 2>(A, ak[1], symv, R);
-  } else {
+    spread_sym<(DIM > 1 ? 1 : 0), DIM>(A, ak[1], symv, R);
+  }
+  {
+    // 1D: its faces; 3D: the z-faces (lanes with a_z in {0, 3})
+    constexpr int K0 = DIM >= 2 ? 2 : 0;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) {
+    for (int k = K0; k < DIM; ++k) {
       const int S = 1 << (2 * k);
       const int akk = ak[k];
       double symv[NC + 1];

@@ -275,26 +275,39 @@ def test_advance_matches_rk_steps(name, ne, steps):
         assert abs(m1["integral"][f] - m2["integral"][f]) <= 1e-13 * (abs(m2["integral"][f]) + 1e-300)
 
 
-@pytest.mark.parametrize("name,ne", [("drop2d", (136, 136)), ("rt3d", (20, 20, 12))])
-def test_advance_two_level_dt(name, ne):
-    """Grids with more than 1024 rate records reduce each step's dt in two
-    small kernels instead of inside the first stage: still the same states,
-    bit for bit, as dg2p_max_dt + dg2p_rk_step, and the same elapsed time."""
+def _advance_vs_rk_steps(name, ne, steps=3):
     cfg, om, prm, U0, mesh, P = gpu_case(name, ne)
     dg = _dg()
     A = U0.cuda().contiguous()
     B = A.clone()
     t = torch.zeros(1, dtype=torch.float64, device="cuda")
     last = torch.zeros(1, dtype=torch.float64, device="cuda")
-    dg.advance(mesh, P, A, 3, cfl=0.1, t=t, dt_last=last)
+    dg.advance(mesh, P, A, steps, cfl=0.1, t=t, dt_last=last)
     tsum = 0.0
-    for _ in range(3):
+    for _ in range(steps):
         dt = dg.max_dt(mesh, P, B, cfl=0.1)
         dg.rk_step(mesh, P, B, dt)
         tsum += float(dt.cpu())
     assert torch.equal(A, B)
     assert float(t.cpu()) == tsum or abs(float(t.cpu()) - tsum) <= 1e-15 * tsum
     assert float(last.cpu()) == float(dt.cpu())
+
+
+@pytest.mark.parametrize("name,ne", [("drop2d", (136, 136)), ("rt3d", (20, 20, 12))])
+def test_advance_two_level_dt(name, ne):
+    """Grids with more than 1024 rate records reduce each step's dt in two
+    small kernels instead of inside the first stage: still the same states,
+    bit for bit, as dg2p_max_dt + dg2p_rk_step, and the same elapsed time."""
+    _advance_vs_rk_steps(name, ne)
+
+
+@pytest.mark.parametrize("ne", [(128, 128), (125, 128)])
+def test_advance_fused_dt_at_record_limit(ne):
+    """The first stage's own reduction at its limit: 1024 rate records (four
+    per thread, all taken) and 1000 (the last four-record share partly
+    empty) give the same states and dt, bit for bit, as dg2p_max_dt +
+    dg2p_rk_step."""
+    _advance_vs_rk_steps("drop2d", ne)
 
 
 def test_advance_fixed_dt():
