@@ -48,7 +48,7 @@ WORKLOAD_DESC = {
 
 # default timed steps per workload: about 50 ms of GPU time on one MI355X, long
 # enough for the clocks to settle and the event timing to be stable
-DEFAULT_STEPS = {"drop1d": 2000, "drop2d": 1000, "shock2d": 200, "rt3d": 5, "adjoint2d": 1000,
+DEFAULT_STEPS = {"drop1d": 2000, "drop2d": 1000, "shock2d": 200, "rt3d": 20, "adjoint2d": 1000,
                  "waterair2d": 2000, "bubble2d": 2000, "rt2d": 1000}
 
 
