@@ -45,8 +45,10 @@ constexpr int BLOCK = 256;      // threads per workgroup (4 independent waves)
 #ifndef DG2P_WAVES_2D
 #define DG2P_WAVES_2D 3
 #endif
+// hexahedra: two waves (at most 256 VGPRs; their kernels use 194-256, none
+// spills), declared so that the allocator cannot drift to one wave
 #ifndef DG2P_WAVES_3D
-#define DG2P_WAVES_3D 1
+#define DG2P_WAVES_3D 2
 #endif
 // Ends a value's code motion at this point (an empty asm statement that
 // takes and returns the value in a vector register).
