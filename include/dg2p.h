@@ -145,8 +145,9 @@ const char* dg2p_status_string(int status);
 const char* dg2p_last_error(void);
 
 /* Create a mesh handle from a host descriptor.  Validates the descriptor
- * (EINVAL), rejects p != 3 (EUNSUPPORTED).  Host only, allocates no device
- * memory.  *out is owned by the caller until dg2p_destroy_mesh. */
+ * (EINVAL, also for 2^31 or more elements, or more than 2^40 nodes), rejects
+ * p != 3 (EUNSUPPORTED).  Host only, allocates no device memory.  *out is
+ * owned by the caller until dg2p_destroy_mesh. */
 int dg2p_create_mesh(const dg2p_mesh_desc* desc /*host*/, dg2p_mesh* out /*host*/);
 
 /* Release a mesh handle (NULL is accepted). */

@@ -589,6 +589,8 @@ int dg2p_create_mesh(const dg2p_mesh_desc* desc, dg2p_mesh* out) {
   }
   const long long nn = 1LL << (2 * desc->dim);
   if (E > (1LL << 40) / nn) return fail(DG2P_EINVAL, "mesh too large");
+  // element indices are formed in 32 bits inside the kernels
+  if (E >= (1LL << 31)) return fail(DG2P_EINVAL, "mesh has 2^31 or more elements");
   dg2p_mesh_s* m = new dg2p_mesh_s;
   std::memset(m, 0, sizeof(*m));
   m->desc = *desc;

@@ -311,14 +311,7 @@ __global__ __launch_bounds__(BLOCK) void k_vjp_local(KArgs A, VjpIO io) {
 
   // ---- faces and SIPG symmetric term ----
   long long ec[3] = {0, 0, 0};
-  {
-    long long r = e;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      ec[k] = r % A.N[k];
-      r /= A.N[k];
-    }
-  }
+  elem_coords<DIM>(A, e, ec);
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
     const int S = 1 << (2 * k);
@@ -619,14 +612,7 @@ __global__ __launch_bounds__(BLOCK) void k_vjp_gather(KArgs A, VjpIO io) {
 #pragma unroll
     for (int k = 0; k < (VISC ? DIM : 1); ++k) Sb[j][k] = 0.0;
   long long ec[3] = {0, 0, 0};
-  {
-    long long r = e;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      ec[k] = r % A.N[k];
-      r /= A.N[k];
-    }
-  }
+  elem_coords<DIM>(A, e, ec);
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
     const int akk = ak[k];

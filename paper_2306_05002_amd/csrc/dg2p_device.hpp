@@ -684,6 +684,19 @@ __device__ __forceinline__ void block_record(double* v, double* rec, long long b
 }
 
 // Logical workgroup of this physical workgroup (XCD-aware order); -1 if padding.
+// Grid coordinates of element e (x fastest). Element counts are below 2^31
+// (checked when the mesh is created), so 32-bit unsigned division suffices.
+template <int DIM>
+__device__ __forceinline__ void elem_coords(const KArgs& A, long long e, long long* ec) {
+  unsigned r = (unsigned)e;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    const unsigned n = (unsigned)A.N[k];
+    ec[k] = r % n;
+    r /= n;
+  }
+}
+
 __device__ __forceinline__ long long logical_block(const KArgs& A) {
   const long long i = blockIdx.x;
   const long long lb = (i & 7) * A.xcd_chunk + (i >> 3);
@@ -1000,14 +1013,7 @@ __global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs
   }
   // element multi-index and face neighbours
   long long ec[3] = {0, 0, 0};
-  {
-    long long r = e;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      ec[k] = r % A.N[k];
-      r /= A.N[k];
-    }
-  }
+  elem_coords<DIM>(A, e, ec);
   long long enb[DIM];
   bool bndk[DIM];
 #pragma unroll

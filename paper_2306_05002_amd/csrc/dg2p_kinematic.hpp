@@ -134,14 +134,7 @@ __global__ __launch_bounds__(BLOCK) void k_kin_stage(KArgs A, KinIO io) {
   Rpsi = -up;
   // element multi-index
   long long ec[3] = {0, 0, 0};
-  {
-    long long r = e;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      ec[k] = r % A.N[k];
-      r /= A.N[k];
-    }
-  }
+  elem_coords<DIM>(A, e, ec);
   // faces (periodic neighbours)
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
@@ -401,14 +394,7 @@ __global__ __launch_bounds__(BLOCK) void k_reinit_stage(KArgs A, ReinitIO io) {
 #pragma unroll
   for (int k = 0; k < DIM; ++k) R += dk<DIM>(A.GammaEps * g[k], k, L, A);
   long long ec[3] = {0, 0, 0};
-  {
-    long long r = e;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      ec[k] = r % A.N[k];
-      r /= A.N[k];
-    }
-  }
+  elem_coords<DIM>(A, e, ec);
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
     const int S = 1 << (2 * k);

@@ -35,7 +35,8 @@ def test_version_and_status_strings():
     assert dg2p._lib.dg2p_status_string(-1).decode() == "DG2P_EINVAL"
 
 
-@pytest.mark.parametrize("bad", ["dim", "order", "n_elem", "box", "bc", "periodic_pair", "riemann_pressure"])
+@pytest.mark.parametrize("bad", ["dim", "order", "n_elem", "box", "bc", "periodic_pair", "riemann_pressure",
+                                 "elem_count"])
 def test_create_mesh_rejects_bad_descriptors(bad):
     kw = dict(dim=2, n_elem=(4, 4), lo=(0, 0), hi=(1, 1), bc=None, order=3)
     if bad == "dim":
@@ -48,6 +49,8 @@ def test_create_mesh_rejects_bad_descriptors(bad):
         kw["hi"] = (1, -1)
     elif bad == "bc":
         kw["bc"] = [(0, 0), (7, 7)]
+    elif bad == "elem_count":          # element indices are 32-bit inside the kernels
+        kw["n_elem"] = (1 << 16, 1 << 15)
     elif bad == "riemann_pressure":    # a Riemann side needs its far-field pressure
         kw["bc"] = [("slip_wall", "slip_wall"), ("no_slip", "riemann")]
     else:
@@ -56,6 +59,11 @@ def test_create_mesh_rejects_bad_descriptors(bad):
         dg2p.Mesh(kw["dim"], kw["n_elem"], kw["lo"], kw["hi"], kw["bc"], order=kw["order"])
     want = dg2p.EUNSUPPORTED if bad == "order" else dg2p.EINVAL
     assert ei.value.status == want
+
+
+def test_create_mesh_accepts_largest_element_count():
+    m = dg2p.Mesh(2, ((1 << 16) - 1, 1 << 15), (0, 0), (1, 1))
+    assert m.E == (1 << 31) - (1 << 15)
 
 
 def test_create_mesh_accepts_wall_and_riemann_kinds():
