@@ -87,6 +87,9 @@ WALL_KINDS = [
     # 3D: no-slip in x, Riemann top (the column's own top pressure) over a no-slip bottom in z
     ("rt3d", (2, 3, 3), [("no_slip", "no_slip"), ("periodic", "periodic"), ("no_slip", "riemann")],
      {(2, 1): [1.0]}),
+    # 3D: walls across y (the y-face jobs of each z-layer meet the boundary), periodic z
+    ("rt3d", (3, 2, 2), [("periodic", "periodic"), ("no_slip", "riemann"), ("periodic", "periodic")],
+     {(1, 1): [1.0]}),
     # 1D: Riemann inflow side (u = 1 enters) against a no-slip wall
     ("drop1d", (13,), [("riemann", "no_slip")], {(0, 0): [1.0]}),
     # 1D: pressure below the state's at the Riemann side (outflow expansion)
@@ -98,8 +101,9 @@ WALL_KINDS = [
 
 @pytest.mark.parametrize("name,ne,bc,bcs", WALL_KINDS)
 def test_rhs_parity_wall_kinds(name, ne, bc, bcs):
-    """The no-slip and Riemann-invariant ghosts in 1D and 3D (the loop form of
-    the face pass) and on every side of a 2D box."""
+    """The no-slip and Riemann-invariant ghosts in 1D (the loop form of the
+    face pass), on x-, y- and z-sides of hexahedra (x and y faces in the
+    remapped pass, z faces in the loop) and on every side of a 2D box."""
     cfg, om, prm, U0, mesh, P = gpu_case(name, ne, bc=bc, bc_state=bcs)
     Ro = oracle.rhs(U0, om, prm)
     Rg = _dg().rhs(mesh, P, U0.cuda().contiguous()).cpu()
