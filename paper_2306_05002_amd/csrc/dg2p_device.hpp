@@ -515,8 +515,7 @@ __device__ __forceinline__ double rate_of(double wmax, double numax, double Gamm
 // (max is exact, so every workgroup obtains the same value as the separate
 // reduction kernels). First half, at kernel entry so that the record loads
 // overlap those of the stage input: each thread's maximum over its share of
-// the records (independent loads), then its wave's maximum, parked
-// in LDS.
+// the records (independent loads), then its wave's maximum, parked in LDS.
 constexpr int FUSED_RATE_PER_THREAD = 4;
 constexpr long long FUSED_RATE_MAX = FUSED_RATE_PER_THREAD * BLOCK;  // records one workgroup reduces
 __device__ __forceinline__ void fused_dt_load(const KArgs& A, const double* __restrict__ rate,
@@ -683,7 +682,6 @@ __device__ __forceinline__ void block_record(double* v, double* rec, long long b
   }
 }
 
-// Logical workgroup of this physical workgroup (XCD-aware order); -1 if padding.
 // Grid coordinates of element e (x fastest). Element counts are below 2^31
 // (checked when the mesh is created), so 32-bit unsigned division suffices.
 template <int DIM>
@@ -697,6 +695,7 @@ __device__ __forceinline__ void elem_coords(const KArgs& A, long long e, long lo
   }
 }
 
+// Logical workgroup of this physical workgroup (XCD-aware order); -1 if padding.
 __device__ __forceinline__ long long logical_block(const KArgs& A) {
   const long long i = blockIdx.x;
   const long long lb = (i & 7) * A.xcd_chunk + (i >> 3);
