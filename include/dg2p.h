@@ -308,8 +308,8 @@ typedef enum {
   DG2P_K_RATE_FINAL = 3,  /* time-step rate reduction, final pass */
   DG2P_K_MONITOR = 4,     /* monitor reduction */
   DG2P_K_PRIM = 5,        /* initial-condition map */
-  DG2P_K_VJP_LOCAL = 6,   /* adjoint: own-element reverse pass */
-  DG2P_K_VJP_GATHER = 7,  /* adjoint: neighbour-contribution gather pass */
+  DG2P_K_VJP_LOCAL = 6,   /* adjoint: residual VJP (own-element and gather passes) */
+  DG2P_K_VJP_GATHER = 7,  /* reserved (timed together with DG2P_K_VJP_LOCAL) */
   DG2P_K_KIN_STAGE = 8    /* kinematic mode: residual + RK4 stage */
 } dg2p_kernel_kind;
 

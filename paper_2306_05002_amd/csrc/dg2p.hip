@@ -15,6 +15,7 @@
 #include "dg2p_device.hpp"
 #include "dg2p_adjoint.hpp"
 #include "dg2p_kinematic.hpp"
+#include "dg2p_launch.hpp"
 
 using namespace dg2p;
 
@@ -265,83 +266,38 @@ int check_ws(void* work, size_t need) {
 
 dim3 elem_grid(const KArgs& A) { return dim3((unsigned)(8 * A.xcd_chunk)); }
 
-template <int DIM, bool VISC, int PR>
-void launch_ingredients_p(const KArgs& A, const double* U, double* G, double* rec, hipStream_t s) {
-  TimedLaunch t(DG2P_K_INGREDIENTS, s);
-  hipLaunchKernelGGL((k_ingredients<DIM, VISC, PR>), elem_grid(A), dim3(BLOCK), 0, s, A, U, G, rec);
-}
-template <int DIM, bool VISC>
-void launch_ingredients(int prec, const KArgs& A, const double* U, double* G, double* rec, hipStream_t s) {
-  if (prec == DG2P_MIXED_FP32) launch_ingredients_p<DIM, VISC, 1>(A, U, G, rec, s);
-  else if (prec == DG2P_MIXED_BF16) launch_ingredients_p<DIM, VISC, 2>(A, U, G, rec, s);
-  else launch_ingredients_p<DIM, VISC, 0>(A, U, G, rec, s);
-}
-
-template <int DIM, bool VISC, bool CSF, int BCK, int PR>
-void launch_stage_p(int mode, int epi, const KArgs& A, const StageIO& io, hipStream_t s) {
-  TimedLaunch t(DG2P_K_STAGE, s);
-  const dim3 g = elem_grid(A), b(BLOCK);
-  if (mode == 0)
-    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, BCK, 0, 0, PR>), g, b, 0, s, A, io);
-  else if (mode == 1)
-    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, BCK, 1, 1, PR>), g, b, 0, s, A, io);
-  else if (epi == 1)
-    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, BCK, 2, 1, PR>), g, b, 0, s, A, io);
-  else if (epi == 2)
-    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, BCK, 2, 2, PR>), g, b, 0, s, A, io);
-  else if (epi == 3)
-    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, BCK, 2, 3, PR>), g, b, 0, s, A, io);
-  else
-    hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, BCK, 2, 0, PR>), g, b, 0, s, A, io);
-}
-template <int DIM, bool VISC, bool CSF, int BCK>
-void launch_stage_t(int prec, int mode, int epi, const KArgs& A, const StageIO& io, hipStream_t s) {
-  if (prec == DG2P_MIXED_FP32) launch_stage_p<DIM, VISC, CSF, BCK, 1>(mode, epi, A, io, s);
-  else if (prec == DG2P_MIXED_BF16) launch_stage_p<DIM, VISC, CSF, BCK, 2>(mode, epi, A, io, s);
-  else launch_stage_p<DIM, VISC, CSF, BCK, 0>(mode, epi, A, io, s);
-}
-
-template <int DIM, int BCK>
-void launch_stage_b(bool visc, bool csf, int pr, int mode, int epi, const KArgs& A, const StageIO& io,
-                    hipStream_t s) {
-  if (visc && csf) launch_stage_t<DIM, true, true, BCK>(pr, mode, epi, A, io, s);
-  else if (visc) launch_stage_t<DIM, true, false, BCK>(pr, mode, epi, A, io, s);
-  else if (csf) launch_stage_t<DIM, false, true, BCK>(pr, mode, epi, A, io, s);
-  else launch_stage_t<DIM, false, false, BCK>(pr, mode, epi, A, io, s);
-}
-
-template <int DIM>
-void launch_stage_d(const dg2p_mesh_s* m, const dg2p_params* p, int mode, int epi, const KArgs& A,
-                    const StageIO& io, hipStream_t s) {
-  const bool visc = viscous(p), csf = p->sigma != 0.0;
-  const int bck = bc_class(m);
-  const int pr = p->precision;
-  if (bck == 2)
-    launch_stage_b<DIM, 2>(visc, csf, pr, mode, epi, A, io, s);
-  else if (bck == 1)
-    launch_stage_b<DIM, 1>(visc, csf, pr, mode, epi, A, io, s);
-  else
-    launch_stage_b<DIM, 0>(visc, csf, pr, mode, epi, A, io, s);
+template <int PR>
+void stage_dim(int dim, int bck, bool visc, bool csf, int mode, int epi, const KArgs& A, const StageIO& io,
+               hipStream_t s) {
+  if (dim == 1) launch_stage_dp<1, PR>(bck, visc, csf, mode, epi, A, io, s);
+  else if (dim == 2) launch_stage_dp<2, PR>(bck, visc, csf, mode, epi, A, io, s);
+  else launch_stage_dp<3, PR>(bck, visc, csf, mode, epi, A, io, s);
 }
 
 void launch_stage(const dg2p_mesh_s* m, const dg2p_params* p, int mode, int epi, const KArgs& A,
                   const StageIO& io, hipStream_t s) {
-  switch (m->dim) {
-    case 1: launch_stage_d<1>(m, p, mode, epi, A, io, s); break;
-    case 2: launch_stage_d<2>(m, p, mode, epi, A, io, s); break;
-    default: launch_stage_d<3>(m, p, mode, epi, A, io, s); break;
-  }
+  TimedLaunch t(DG2P_K_STAGE, s);
+  const bool visc = viscous(p), csf = p->sigma != 0.0;
+  const int bck = bc_class(m);
+  if (p->precision == DG2P_MIXED_FP32) stage_dim<1>(m->dim, bck, visc, csf, mode, epi, A, io, s);
+  else if (p->precision == DG2P_MIXED_BF16) stage_dim<2>(m->dim, bck, visc, csf, mode, epi, A, io, s);
+  else stage_dim<0>(m->dim, bck, visc, csf, mode, epi, A, io, s);
+}
+
+template <int PR>
+void ingr_dim(int dim, bool visc, const KArgs& A, const double* U, double* G, double* rec, hipStream_t s) {
+  if (dim == 1) launch_ingredients_dp<1, PR>(visc, A, U, G, rec, s);
+  else if (dim == 2) launch_ingredients_dp<2, PR>(visc, A, U, G, rec, s);
+  else launch_ingredients_dp<3, PR>(visc, A, U, G, rec, s);
 }
 
 void launch_ingr(const dg2p_mesh_s* m, const dg2p_params* p, const KArgs& A, const double* U, double* G,
                  double* rec, hipStream_t s) {
+  TimedLaunch t(DG2P_K_INGREDIENTS, s);
   const bool v = viscous(p);
-  const int pr = p->precision;
-  switch (m->dim) {
-    case 1: v ? launch_ingredients<1, true>(pr, A, U, G, rec, s) : launch_ingredients<1, false>(pr, A, U, G, rec, s); break;
-    case 2: v ? launch_ingredients<2, true>(pr, A, U, G, rec, s) : launch_ingredients<2, false>(pr, A, U, G, rec, s); break;
-    default: v ? launch_ingredients<3, true>(pr, A, U, G, rec, s) : launch_ingredients<3, false>(pr, A, U, G, rec, s); break;
-  }
+  if (p->precision == DG2P_MIXED_FP32) ingr_dim<1>(m->dim, v, A, U, G, rec, s);
+  else if (p->precision == DG2P_MIXED_BF16) ingr_dim<2>(m->dim, v, A, U, G, rec, s);
+  else ingr_dim<0>(m->dim, v, A, U, G, rec, s);
 }
 
 void launch_records(const dg2p_mesh_s* m, const dg2p_params* p, const KArgs& A, const double* U, double* rec,
@@ -428,24 +384,6 @@ bool all_periodic(const dg2p_mesh_s* m) {
   return true;
 }
 
-template <int DIM, bool VISC, bool CSF>
-void launch_vjp_d(const KArgs& A, const VjpIO& io, hipStream_t s) {
-  {
-    TimedLaunch t(DG2P_K_VJP_LOCAL, s);
-    hipLaunchKernelGGL((k_vjp_local<DIM, VISC, CSF>), elem_grid(A), dim3(BLOCK), 0, s, A, io);
-  }
-  TimedLaunch t(DG2P_K_VJP_GATHER, s);
-  hipLaunchKernelGGL((k_vjp_gather<DIM, VISC>), elem_grid(A), dim3(BLOCK), 0, s, A, io);
-}
-
-template <int DIM>
-void launch_vjp_dim(bool visc, bool csf, const KArgs& A, const VjpIO& io, hipStream_t s) {
-  if (visc && csf) launch_vjp_d<DIM, true, true>(A, io, s);
-  else if (visc) launch_vjp_d<DIM, true, false>(A, io, s);
-  else if (csf) launch_vjp_d<DIM, false, true>(A, io, s);
-  else launch_vjp_d<DIM, false, false>(A, io, s);
-}
-
 // Ub (+)= (dR/dU)^T Rb at state U; sigma cotangent added to *sigb when non-NULL.
 void residual_vjp(const dg2p_mesh_s* m, const dg2p_params* p, const KArgs& A, const double* U, const double* G,
                   const double* Rb, double* T, double* FB, double* rec, double* Ub, int accumulate, double* sigb,
@@ -453,10 +391,13 @@ void residual_vjp(const dg2p_mesh_s* m, const dg2p_params* p, const KArgs& A, co
   const bool visc = viscous(p);
   const bool csf = p->sigma != 0.0 || sigb != nullptr;
   VjpIO io{U, G, Rb, T, FB, rec, Ub, accumulate};
-  switch (m->dim) {
-    case 1: launch_vjp_dim<1>(visc, csf, A, io, s); break;
-    case 2: launch_vjp_dim<2>(visc, csf, A, io, s); break;
-    default: launch_vjp_dim<3>(visc, csf, A, io, s); break;
+  {
+    TimedLaunch t(DG2P_K_VJP_LOCAL, s);
+    switch (m->dim) {
+      case 1: launch_vjp_dim<1>(visc, csf, A, io, s); break;
+      case 2: launch_vjp_dim<2>(visc, csf, A, io, s); break;
+      default: launch_vjp_dim<3>(visc, csf, A, io, s); break;
+    }
   }
   if (sigb && csf) hipLaunchKernelGGL(k_sum_add, dim3(1), dim3(BLOCK), 0, s, rec, A.nblocks, sigb);
 }

@@ -46,15 +46,17 @@ constexpr CoefTabT make_coef_tab_t() {
     }
   return t;
 }
-__constant__ CoefTabT kCoefT = make_coef_tab_t();
+static __constant__ CoefTabT kCoefT = make_coef_tab_t();
 
 template <int DIM>
-__device__ __forceinline__ void lane_coeffs_T(const int* ak, LaneD<DIM>& L) {
+__device__ __forceinline__ void lane_coeffs_T(const KArgs& A, const int* ak, LaneD<DIM>& L) {
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) L.c[k][r] = kCoefT.c[k][ak[k]][r];
   }
+  // transposed z-operator (1/J_z) D^T on the matrix cores: entry [a_x][a_z] = D[a_z][a_x]
+  L.mz = DIM == 3 ? kCoef.d[ak[DIM == 3 ? 2 : 0]][ak[0]] * A.Jinv[2] : 0.0;
 }
 
 // Sum of x over the 4 lanes of the lane's line along axis k.
@@ -279,7 +281,7 @@ __global__ __launch_bounds__(BLOCK) void k_vjp_local(KArgs A, VjpIO io) {
   for (int k = 0; k < DIM; ++k) ak[k] = (node >> (2 * k)) & 3;
   LaneD<DIM> L, LT;
   lane_coeffs<DIM>(A, ak, L);
-  lane_coeffs_T<DIM>(ak, LT);
+  lane_coeffs_T<DIM>(A, ak, LT);
   const long long fs = A.E * NN;
   const long long o = e * NN + node;
 
@@ -589,7 +591,7 @@ __global__ __launch_bounds__(BLOCK) void k_vjp_gather(KArgs A, VjpIO io) {
   for (int k = 0; k < DIM; ++k) ak[k] = (node >> (2 * k)) & 3;
   LaneD<DIM> L, LT;
   lane_coeffs<DIM>(A, ak, L);
-  lane_coeffs_T<DIM>(ak, LT);
+  lane_coeffs_T<DIM>(A, ak, LT);
   const long long fs = A.E * NN;
   const long long o = e * NN + node;
   double q[NF], qb[NF];
@@ -656,7 +658,7 @@ __global__ __launch_bounds__(BLOCK) void k_vjp_gather(KArgs A, VjpIO io) {
 
 // Stage combination of the RK-step reverse pass (one thread per value):
 // Ub += an X;  Xo = ax X (if Xo);  Rb = ar dt X.
-__global__ void k_vjp_combine(long long n, const double* X, const double* dt, double an, int init, double* Ub,
+static __global__ __attribute__((unused)) void k_vjp_combine(long long n, const double* X, const double* dt, double an, int init, double* Ub,
                               double ax, double* Xo, double ar, double* Rb) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -667,7 +669,7 @@ __global__ void k_vjp_combine(long long n, const double* X, const double* dt, do
 }
 
 // Fixed-order sum of n per-workgroup values added to *out.
-__global__ __launch_bounds__(BLOCK) void k_sum_add(const double* __restrict__ v, long long n, double* out) {
+static __global__ __attribute__((unused)) __launch_bounds__(BLOCK) void k_sum_add(const double* __restrict__ v, long long n, double* out) {
   double acc = 0.0;
   for (long long i = threadIdx.x; i < n; i += BLOCK) acc += v[i];
   __shared__ double sh[BLOCK / 64];

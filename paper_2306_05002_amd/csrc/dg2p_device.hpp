@@ -123,6 +123,8 @@ struct CoefTab {
   double c[3][4][4];
   double sp[2][4];
   double w[4];
+  double d[4][4];   // D itself (operator entries of the matrix-core z-contractions)
+  double szt[4][4]; // [a][b] = D[b][a] / w_a for b in {0, 3}, else 0: the SIPG spread along a line
 };
 constexpr CoefTab make_coef_tab() {
   CoefTab t{};
@@ -135,10 +137,14 @@ constexpr CoefTab make_coef_tab() {
     t.sp[0][a] = GLL.D[0][a] / GLL.w[a];
     t.sp[1][a] = GLL.D[3][a] / GLL.w[a];
     t.w[a] = GLL.w[a];
+    for (int b = 0; b < 4; ++b) {
+      t.d[a][b] = GLL.D[a][b];
+      t.szt[a][b] = (b == 0 || b == 3) ? GLL.D[b][a] / GLL.w[a] : 0.0;
+    }
   }
   return t;
 }
-__constant__ CoefTab kCoef = make_coef_tab();
+static __constant__ CoefTab kCoef = make_coef_tab();
 
 struct KArgs {
   long long E;
@@ -217,20 +223,35 @@ __device__ __forceinline__ double rrot(double v) {
   return dpp64<0x120 + 4 * N>(v);
 }
 
-// Per-lane rotated derivative coefficients for each axis.
+// Per-lane rotated derivative coefficients for each axis; for hexahedra also
+// the lane's entry of the z-contraction operator on the matrix cores (below).
 template <int DIM>
 struct LaneD {
   double c[DIM][4];
+  double mz;
 };
+
+// ---- z-contractions of a hexahedron on the matrix cores ------------------------
+// v_mfma_f64_4x4x4f64 multiplies four independent 4x4 FP64 blocks in one wave
+// instruction: lane l supplies A[l & 3][l >> 4] and B[l >> 4][l & 3] of block
+// (l >> 2) & 3 and receives C[l >> 4][l & 3] (measured on gfx950).  With the
+// node index a_x + 4 a_y + 16 a_z of the lane, B = f is the field itself
+// (block = a_y, row = a_z, column = a_x), so C = M f contracts every z-line of
+// the element with the 4x4 operator M, and the result lands on its own node:
+// no lane exchange.  A lane holds the entry M[a_x][a_z] of the operator.
+__device__ __forceinline__ double mfma_z(double m, double f, double acc) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(m, f, acc, 0, 0, 0);
+}
 
 template <int DIM>
 __device__ __forceinline__ void lane_coeffs(const KArgs& A, const int* ak, LaneD<DIM>& L) {
-  (void)A;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) L.c[k][r] = kCoef.c[k][ak[k]][r];
   }
+  // z-derivative operator (1/J_z) D: entry [a_x][a_z]
+  L.mz = DIM == 3 ? kCoef.d[ak[0]][ak[DIM == 3 ? 2 : 0]] * A.Jinv[2] : 0.0;
 }
 
 // Sum over the 4 nodes of the lane's line along axis K of D[a_K][b] f_b.
@@ -242,25 +263,24 @@ __device__ __forceinline__ double contract(double f, const LaneD<DIM>& L) {
     r = fma(c[1], qrot<1>(f), r);
     r = fma(c[2], qrot<2>(f), r);
     return fma(c[3], qrot<3>(f), r);
-  } else if constexpr (K == 1) {
+  } else {
+    static_assert(K == 1, "z-contractions run on the matrix cores (mfma_z)");
     double r = c[0] * f;
     r = fma(c[1], rrot<1>(f), r);
     r = fma(c[2], rrot<2>(f), r);
     return fma(c[3], rrot<3>(f), r);
-  } else {
-    double r = c[0] * f;
-    r = fma(c[1], __shfl_xor(f, 16), r);
-    r = fma(c[2], __shfl_xor(f, 32), r);
-    return fma(c[3], __shfl_xor(f, 48), r);
   }
 }
 
+// Derivative along axis k: (1/J_k) sum_b D[a_k][b] f_b.  Must be called by
+// the whole wave (uniform control flow): the z-contraction is a wave-wide
+// matrix instruction.
 template <int DIM>
 __device__ __forceinline__ double dk(double f, int k, const LaneD<DIM>& L, const KArgs& A) {
   if (k == 0) return contract<0, DIM>(f, L) * A.Jinv[0];
   if constexpr (DIM > 1)
     if (k == 1) return contract<(DIM > 1 ? 1 : 0), DIM>(f, L) * A.Jinv[1];
-  if constexpr (DIM > 2) return contract<(DIM > 2 ? 2 : 0), DIM>(f, L) * A.Jinv[2];
+  if constexpr (DIM > 2) return mfma_z(L.mz, f, 0.0);
   return 0.0;
 }
 
@@ -964,6 +984,19 @@ __device__ __forceinline__ void face_flux(const KArgs& A, int kd, int side, bool
 template <int K, int DIM>
 __device__ __forceinline__ void spread_sym(const KArgs& A, int akk, const double* symv, double* R) {
   constexpr int NC = DIM + 3;
+  if constexpr (K == 2) {
+    // hexahedron z-lines on the matrix cores: R += S symv with
+    // S[a][b] = D[b][a] / (2 w_a J_z^2) for the line ends b in {0, 3}
+    // (akk is a_z; the lane's operator entry is S[a_x][a_z])
+    const int ax = __lane_id() & 3;
+    const double m = kCoef.szt[ax][akk] * A.hJ2inv[2];
+#pragma unroll
+    for (int i = 0; i <= NC; ++i) {
+      const int f = (i < NC) ? i : 3 + DIM;
+      R[f] = mfma_z(m, symv[i], R[f]);
+    }
+    return;
+  }
   const double wlo = kCoef.sp[0][akk] * A.hJ2inv[K];
   const double whi = kCoef.sp[1][akk] * A.hJ2inv[K];
 #pragma unroll
@@ -1433,7 +1466,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_records(const double* __restri
 // nu_max / h_min) / h_min with nu_max = max(Gamma eps, max mu/rho); dt = cfl / rate.
 // One workgroup of FIN_THREADS threads.
 constexpr int FIN_THREADS = 1024;
-__global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double* __restrict__ rec, long long n,
+static __global__ __attribute__((unused)) __launch_bounds__(FIN_THREADS) void k_finalize(const double* __restrict__ rec, long long n,
                                                           double GammaEps, int dim, int nf, double hmin,
                                                           double cfl, const double* dt_fixed, double* dt,
                                                           double* t, dg2p_monitors* mon) {
@@ -1460,7 +1493,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double* __restri
 
 // Final reduction of rate records (time step only): *dt = cfl / rate (or
 // *dt_fixed), *t += dt.
-__global__ __launch_bounds__(FIN_THREADS) void k_finalize_rate(const double* __restrict__ rec, long long n,
+static __global__ __attribute__((unused)) __launch_bounds__(FIN_THREADS) void k_finalize_rate(const double* __restrict__ rec, long long n,
                                                                double GammaEps, int dim, double hmin, double cfl,
                                                                const double* dt_fixed, double* dt, double* t) {
   __shared__ double red[RATE];

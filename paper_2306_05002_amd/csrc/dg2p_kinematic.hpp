@@ -272,7 +272,7 @@ __global__ __launch_bounds__(BLOCK) void k_kin_errors(KArgs A, const double* __r
 }
 
 // Sum n records of KERR slots in a fixed order (one workgroup): out[s], s < nout.
-__global__ __launch_bounds__(FIN_THREADS) void k_kin_sum(const double* __restrict__ rec, long long n, int nout,
+static __global__ __attribute__((unused)) __launch_bounds__(FIN_THREADS) void k_kin_sum(const double* __restrict__ rec, long long n, int nout,
                                                          double* __restrict__ out) {
   const int s = threadIdx.x % KERR;
   double acc = 0.0;

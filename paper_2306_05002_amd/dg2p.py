@@ -4,8 +4,9 @@ Argument marshalling only: every step of the residual, the RK stages, the
 time-step reduction, the monitors and the initial-condition map runs in the
 library's HIP kernels.  Torch provides device memory (tensors), streams and
 the workspace buffers.  Importing this module loads ``libdg2p.so`` from the
-package directory and raises ImportError if it is missing: there is no
-fallback path.
+package directory (or the file named by the environment variable
+DG2P_LIBRARY, for comparing two builds) and raises ImportError if it is
+missing: there is no fallback path.
 """
 
 import ctypes
@@ -15,10 +16,10 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdg2p.so")
+LIB_PATH = os.environ.get("DG2P_LIBRARY") or os.path.join(_HERE, "libdg2p.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"libdg2p.so not built at {LIB_PATH}; run __graft_entry__.build()")
+    raise ImportError(f"libdg2p.so not found at {LIB_PATH}; run __graft_entry__.build()")
 _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, EHIP, ENONPHYS, EUNSUPPORTED, EWORKSPACE = 0, -1, -2, -3, -4, -5
