@@ -199,6 +199,27 @@ int dg2p_max_dt(dg2p_mesh m, const dg2p_params* p /*host*/, const double* U /*de
 int dg2p_rk_step(dg2p_mesh m, const dg2p_params* p /*host*/, double* U /*device, in/out*/,
                  const double* dt /*device*/, void* work /*device*/, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the step of
+ * dg2p_rk_step (same kernels, bitwise the same result) with its workspace in
+ * a static device array of the library instead of a caller workspace.  That
+ * array holds dg2p_noalloc_scratch_bytes() = 64 MiB on every GPU the library
+ * runs on, from the first call on that device until the process ends.  The
+ * call allocates nothing and calls no hipMalloc / hipFree; meshes whose
+ * DG2P_OP_RK_STEP workspace (dg2p_workspace_size) exceeds the array are
+ * rejected with DG2P_EWORKSPACE before anything is launched (e.g. the 2D
+ * 128 x 128 grid fits: 34 MiB inviscid, 43 MiB viscous).  The calling
+ * thread's current device must be the one `stream` belongs to.  Every call on
+ * a GPU shares that GPU's array: calls that overlap on one GPU (two streams,
+ * two threads) race and give wrong results; calls in stream order are safe.
+ * Nothing is carried between calls (every value a call reads from the array,
+ * it wrote first).  U, dt: as for dg2p_rk_step. */
+int dg2p_rk_step_noalloc(dg2p_mesh m, const dg2p_params* p /*host*/, double* U /*device, in/out*/,
+                         const double* dt /*device*/, void* stream);
+
+/* Size in bytes of the static device scratch of dg2p_rk_step_noalloc. */
+size_t dg2p_noalloc_scratch_bytes(void);
+
 /* Advance U in place by n_steps SSP-RK3 steps without host synchronisation.
  * Each step's dt is cfl / max_rate of the step's initial state (the rule of
  * dg2p_max_dt), reduced on the device, or *dt_fixed when dt_fixed != NULL

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "../../include/dg2p.h"
@@ -18,6 +19,14 @@
 #include "dg2p_launch.hpp"
 
 using namespace dg2p;
+
+// Device scratch of dg2p_rk_step_noalloc (callers that cannot allocate device
+// memory): a file-scope array that every GPU running the library holds until
+// the process ends.  Host code never passes `scratch` itself to a kernel (its
+// name is a host-side stand-in); it uses the address hipGetSymbolAddress
+// returns on each device (noalloc_scratch below).
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
 
 struct dg2p_mesh_s {
   dg2p_mesh_desc desc;
@@ -487,6 +496,51 @@ void reinit_stage(const dg2p_mesh_s* m, int mode, const KArgs& A, const ReinitIO
   else reinit_stage_d<3>(mode, A, io, s);
 }
 
+// One SSP-RK3 step with the workspace `work` (carved as for DG2P_OP_RK_STEP).
+void rk_step_launch(const dg2p_mesh_s* m, const dg2p_params* p, double* U, const double* dt, void* work,
+                    hipStream_t s) {
+  KArgs A = make_args(m, p);
+  Work w = carve(m, p, DG2P_OP_RK_STEP, work);
+  launch_ingr(m, p, A, U, w.G0, w.rec, s);
+  // stage 1: U1 = U + dt R(U)
+  StageIO io1{U, w.G0, nullptr, w.U1, w.G1, w.rec, dt};
+  launch_stage(m, p, 1, 1, A, io1, s);
+  // stage 2: U2 = 3/4 U + 1/4 (U1 + dt R(U1))
+  A.rk_a = 0.75;
+  A.rk_b = 0.25;
+  StageIO io2{w.U1, w.G1, U, w.U2, w.G0, w.rec, dt};
+  launch_stage(m, p, 2, 1, A, io2, s);
+  // stage 3: U <- 1/3 U + 2/3 (U2 + dt R(U2)); each node reads its own U before writing it
+  A.rk_a = 1.0 / 3.0;
+  A.rk_b = 2.0 / 3.0;
+  StageIO io3{w.U2, w.G0, U, U, nullptr, nullptr, dt};
+  launch_stage(m, p, 2, 0, A, io3, s);
+}
+
+// Per-device address of `scratch`, looked up once per device (with that
+// device current) by hipGetSymbolAddress; never the host-side name.
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+int noalloc_scratch(void** out) {
+  int dev = -1;
+  int st = hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (st) return st;
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(DG2P_EUNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    st = hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (st) return st;
+    if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255))
+      return fail(DG2P_EHIP, "hipGetSymbolAddress(scratch) returned an unusable address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return DG2P_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -687,25 +741,28 @@ int dg2p_rk_step(dg2p_mesh m, const dg2p_params* p, double* U, const double* dt,
   if (st) return st;
   st = check_ws(work, work_bytes(m, p, DG2P_OP_RK_STEP));
   if (st) return st;
-  KArgs A = make_args(m, p);
-  Work w = carve(m, p, DG2P_OP_RK_STEP, work);
-  hipStream_t s = (hipStream_t)stream;
-  launch_ingr(m, p, A, U, w.G0, w.rec, s);
-  // stage 1: U1 = U + dt R(U)
-  StageIO io1{U, w.G0, nullptr, w.U1, w.G1, w.rec, dt};
-  launch_stage(m, p, 1, 1, A, io1, s);
-  // stage 2: U2 = 3/4 U + 1/4 (U1 + dt R(U1))
-  A.rk_a = 0.75;
-  A.rk_b = 0.25;
-  StageIO io2{w.U1, w.G1, U, w.U2, w.G0, w.rec, dt};
-  launch_stage(m, p, 2, 1, A, io2, s);
-  // stage 3: U <- 1/3 U + 2/3 (U2 + dt R(U2)); each node reads its own U before writing it
-  A.rk_a = 1.0 / 3.0;
-  A.rk_b = 2.0 / 3.0;
-  StageIO io3{w.U2, w.G0, U, U, nullptr, nullptr, dt};
-  launch_stage(m, p, 2, 0, A, io3, s);
+  rk_step_launch(m, p, U, dt, work, (hipStream_t)stream);
   return hip_check(hipGetLastError(), "rk_step launch");
 }
+
+int dg2p_rk_step_noalloc(dg2p_mesh m, const dg2p_params* p, double* U, const double* dt, void* stream) {
+  g_last_error.clear();
+  if (!m || !U || !dt) return fail(DG2P_EINVAL, "mesh, U and dt must be non-NULL");
+  int st = check_params(m, p);
+  if (st) return st;
+  const size_t need = work_bytes(m, p, DG2P_OP_RK_STEP);
+  if (need > NOALLOC_SCRATCH_BYTES)
+    return fail(DG2P_EWORKSPACE, "dg2p_rk_step_noalloc: this mesh needs " + std::to_string(need) +
+                                     " bytes of scratch; the library's static scratch holds " +
+                                     std::to_string(NOALLOC_SCRATCH_BYTES) + " (use dg2p_rk_step with a workspace)");
+  void* work = nullptr;
+  st = noalloc_scratch(&work);
+  if (st) return st;
+  rk_step_launch(m, p, U, dt, work, (hipStream_t)stream);
+  return hip_check(hipGetLastError(), "rk_step_noalloc launch");
+}
+
+size_t dg2p_noalloc_scratch_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
 
 int dg2p_advance(dg2p_mesh m, const dg2p_params* p, double* U, int n_steps, double cfl, const double* dt_fixed,
                  double* t, double* dt_last, dg2p_monitors* mon, double p_ref, const double* u_ref, void* work,

@@ -74,6 +74,8 @@ _SIG = {
     "dg2p_rhs": ([_vp, ctypes.POINTER(Params), _dp, _dp, _vp, _vp], _i),
     "dg2p_max_dt": ([_vp, ctypes.POINTER(Params), _dp, _d, _dp, _vp, _vp, _vp], _i),
     "dg2p_rk_step": ([_vp, ctypes.POINTER(Params), _dp, _dp, _vp, _vp], _i),
+    "dg2p_rk_step_noalloc": ([_vp, ctypes.POINTER(Params), _dp, _dp, _vp], _i),
+    "dg2p_noalloc_scratch_bytes": ([], ctypes.c_size_t),
     "dg2p_compute_monitors": ([_vp, ctypes.POINTER(Params), _dp, _d, _dp, _vp, _vp, _vp], _i),
     "dg2p_advance": ([_vp, ctypes.POINTER(Params), _dp, _i, _d, _dp, _dp, _dp, _vp, _d, _vp, _vp, _vp], _i),
     "dg2p_rhs_vjp": ([_vp, ctypes.POINTER(Params), _dp, _dp, _dp, _dp, _vp, _vp], _i),
@@ -269,6 +271,22 @@ def rk_step(mesh, params, U, dt, stream=None):
     _check(_lib.dg2p_rk_step(mesh.handle, ctypes.byref(params), _ptr(U), _ptr(dt), ws, _stream(stream)),
            "dg2p_rk_step")
     return U
+
+
+def rk_step_noalloc(mesh, params, U, dt, stream=None):
+    """dg2p_rk_step_noalloc: the step of rk_step with the library's static
+    device scratch instead of a workspace (no device allocation anywhere on
+    the call path).  Raises Dg2pError (DG2P_EWORKSPACE) for meshes whose
+    workspace exceeds noalloc_scratch_bytes()."""
+    U = _as_state(mesh, U)
+    _check(_lib.dg2p_rk_step_noalloc(mesh.handle, ctypes.byref(params), _ptr(U), _ptr(dt), _stream(stream)),
+           "dg2p_rk_step_noalloc")
+    return U
+
+
+def noalloc_scratch_bytes():
+    """Bytes of the static device scratch behind rk_step_noalloc."""
+    return int(_lib.dg2p_noalloc_scratch_bytes())
 
 
 def advance(mesh, params, U, n_steps, cfl=0.1, dt_fixed=None, t=None, dt_last=None, mon=None,

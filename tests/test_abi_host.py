@@ -122,3 +122,19 @@ def test_binding_enums_match_header():
     assert ops["kin_rhs"] == dg2p.OP_KIN_RHS and ops["kin_aux"] == dg2p.OP_KIN_AUX
     assert ctypes.sizeof(dg2p.MeshDesc) == 4 * 2 + 4 * 3 + 8 * 6 + 4 * 6 + 4 + 8 * 48   # incl. 4 padding bytes
     assert ctypes.sizeof(dg2p.Monitors) == 8 * 15
+
+
+def test_noalloc_step_refuses_oversized_mesh_before_any_device_call():
+    """dg2p_rk_step_noalloc checks the mesh's workspace against its static
+    scratch (64 MiB) on the host and returns DG2P_EWORKSPACE without touching
+    the device (the pointers below are never dereferenced)."""
+    assert dg2p.noalloc_scratch_bytes() == 64 << 20
+    P = dg2p.make_params(workloads.config("drop2d")["params"])
+    mesh = dg2p.Mesh(2, (512, 256), (0.0, 0.0), (2.0, 1.0))      # two 117 MB stage states
+    assert mesh.workspace_bytes(P, dg2p.OP_RK_STEP) > dg2p.noalloc_scratch_bytes()
+    fake = ctypes.c_void_p(1 << 20)
+    st = dg2p._lib.dg2p_rk_step_noalloc(mesh.handle, ctypes.byref(P), fake, fake, None)
+    assert st == dg2p.EWORKSPACE
+    assert "static scratch" in dg2p._lib.dg2p_last_error().decode()
+    st = dg2p._lib.dg2p_rk_step_noalloc(mesh.handle, ctypes.byref(P), None, fake, None)
+    assert st == dg2p.EINVAL
