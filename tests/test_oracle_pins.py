@@ -343,6 +343,98 @@ def test_curvature_converges_to_circle():
     assert math.log2(errs[0] / errs[1]) > 1.7 and math.log2(errs[1] / errs[2]) > 1.7
 
 
+def _csf_source(d, N, eps, R, u=None, sigma=1.0):
+    """CSF part of the residual, R(sigma) - R(0) (the residual is affine in
+    sigma and sigma enters only the surface-tension source), for a droplet /
+    sphere of radius R centred in the periodic unit box: psi = r - R,
+    alpha = sigmoid(psi/eps) (air outside), uniform P = 1, velocity u
+    (uniform, default at rest)."""
+    prm1 = oracle.Params(eps=eps, sigma=sigma)
+    prm0 = oracle.Params(eps=eps, sigma=0.0)
+    mesh = oracle.OracleMesh(d, 3, (N,) * d, (0.0,) * d, (1.0,) * d)
+    X = mesh.node_coords()
+    r = torch.sqrt(sum((X[k] - 0.5) ** 2 for k in range(d)))
+    psi = r - R
+    one = torch.ones_like(r)
+    uu = torch.zeros((d,) + r.shape) if u is None else torch.stack([u[k] * one for k in range(d)])
+    U = oracle.prim_to_cons(torch.sigmoid(psi / eps), psi, one, 10 * one, uu, one, prm1)
+    return mesh, oracle.rhs(U, mesh, prm1) - oracle.rhs(U, mesh, prm0)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_csf_force_on_half_droplet_is_the_laplace_force(d):
+    """Continuum surface force sigma kappa n delta_Gamma (Section "Five
+    equation model", momentum equation) of a droplet at rest: integrated over
+    the half of the box beyond the centre it is the force the other half's
+    surface tension exerts, inward and equal to the Laplace pressure jump
+    sigma (d-1)/R times the cut's area: -2 sigma x in 2D (cut length 2R,
+    jump sigma/R), -2 pi sigma R x in 3D (cut area pi R^2, jump 2 sigma/R).
+    Converges as h, eps -> 0 (eps = h/2); the transverse component vanishes.
+    Fails on a flipped force sign, a dropped delta_Gamma, a kappa of the wrong
+    sign, n taken as grad alpha, or delta_Gamma taken from psi."""
+    R, sigma = 0.25, 1.0
+    want = -2.0 * sigma if d == 2 else -2.0 * math.pi * sigma * R
+    grids = (16, 32, 64) if d == 2 else (8, 24)
+    errs = []
+    for N in grids:
+        mesh, dR = _csf_source(d, N, 0.5 / N, R, sigma=sigma)
+        W = mesh.node_weights()
+        right = mesh.elem_multi(torch.arange(mesh.E))[0] >= N // 2
+        Fx = float((dR[2][right] * W).sum())
+        Fy = float((dR[3][right] * W).sum())
+        assert abs(Fy) < 1e-12
+        errs.append(abs(Fx - want) / abs(want))
+    assert errs[-1] < (1e-4 if d == 2 else 5e-4), errs
+    assert all(errs[i + 1] < 0.5 * errs[i] for i in range(len(errs) - 1)), errs
+
+
+def test_csf_energy_source_is_the_work_of_the_csf_force():
+    """The surface-tension term of the energy equation is the work of the CSF
+    force, sigma kappa (u.n) delta_Gamma = u . (sigma kappa n delta_Gamma), node
+    by node (uniform u, droplet of radius 0.2; the partial densities and
+    alpha carry no sigma term).  Fails on u.grad alpha in place of u.n, a
+    missing energy term, or a missing sigma term on the densities' side."""
+    u = (0.3, -0.7)
+    mesh, dR = _csf_source(2, 12, 0.02, 0.2, u=u, sigma=0.05)
+    work = u[0] * dR[2] + u[1] * dR[3]
+    scale = float(dR[4].abs().max())
+    assert scale > 1e-3
+    assert float((dR[4] - work).abs().max()) < 1e-13 * scale
+    for f in (0, 1, 5, 6):
+        assert float(dR[f].abs().max()) == 0.0
+
+
+def test_time_step_rule_viscous_branch():
+    """Time-step rule with viscosity: nu_max = max(Gamma eps, max mu/rho).
+    Pure air (alpha = 1, ideal gas gamma = 1.4) with rho = 1.4, P = 1 has
+    sound speed 1 exactly; with u = (0.5, -0.25) the wave term is
+    |u_x| + |u_y| + d c = 2.75.  Viscosity mu_1 = 0.05 dominates Gamma eps:
+    rate = (2.75 + 16 * 2 * (0.05 / 1.4) / h) / h; with mu_1 = 1e-6 the
+    interface term Gamma eps does.  A second, two-density state (rho = 1.4 in
+    the left half, 0.7 in the right) has its largest mu/rho on the light side.
+    Fails on mu in place of mu/rho, a missing (p+1)^2 d factor, or a sum in
+    place of the max."""
+    d, N = 2, 4
+    mesh = oracle.OracleMesh(d, 3, (N, N), (0.0, 0.0), (1.0, 1.0))
+    h = 1.0 / N
+    one = torch.ones(mesh.E, mesh.nn)
+    u = torch.stack([0.5 * one, -0.25 * one])
+    for mu1, nu_want in ((0.05, 0.05 / 1.4), (1e-6, 0.5 * 0.03)):
+        prm = oracle.Params(eps=0.03, Gamma=0.5, mu=(mu1, 2 * mu1))
+        U = oracle.prim_to_cons(one, 0 * one, 1.4 * one, 10 * one, u, one, prm)
+        rate = (2.75 + 16 * d * nu_want / h) / h
+        assert abs(oracle.max_rate(U, mesh, prm) - rate) < 1e-13 * rate
+    # two densities: rho = 0.7 on the right half (P = 0.5 keeps c = 1 there)
+    X = mesh.node_coords()
+    right = X[0] > 0.5
+    rho = torch.where(right, 0.7 * one, 1.4 * one)
+    P = torch.where(right, 0.5 * one, one)
+    prm = oracle.Params(eps=0.03, Gamma=0.5, mu=(0.05, 0.1))
+    U = oracle.prim_to_cons(one, 0 * one, rho, 10 * one, u, P, prm)
+    rate = (2.75 + 16 * d * (0.05 / 0.7) / h) / h
+    assert abs(oracle.max_rate(U, mesh, prm) - rate) < 1e-13 * rate
+
+
 def test_gravity_source():
     """Uniform state, gravity only: R_rhou = rho g, R_rhoE = rho g.u."""
     prm = oracle.Params(eps=0.01, g=(0.3, -1.0, 0.0))
