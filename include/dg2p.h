@@ -187,7 +187,8 @@ int dg2p_rhs(dg2p_mesh m, const dg2p_params* p /*host*/, const double* U /*devic
              double* R /*device*/, void* work /*device*/, void* stream);
 
 /* Time step dt = cfl / max_rate (rule above, recomputed from U) written to
- * the device scalar *dt; if mon != NULL also mon->max_rate and mon->dt.
+ * the device scalar *dt; if mon != NULL also mon->max_rate and mon->dt.  A
+ * node whose closure fails (NaN sound speed) makes max_rate and dt NaN.
  * work: dg2p_workspace_size(DG2P_OP_MAX_DT) bytes. */
 int dg2p_max_dt(dg2p_mesh m, const dg2p_params* p /*host*/, const double* U /*device*/,
                 double cfl, double* dt /*device*/, dg2p_monitors* mon /*device, nullable*/,
@@ -232,6 +233,22 @@ int dg2p_advance(dg2p_mesh m, const dg2p_params* p /*host*/, double* U /*device,
                  double cfl, const double* dt_fixed /*device, nullable*/, double* t /*device, nullable*/,
                  double* dt_last /*device, nullable*/, dg2p_monitors* mon /*device, nullable*/,
                  double p_ref, const double* u_ref /*host, nullable*/, void* work /*device*/, void* stream);
+
+/* dg2p_advance with the monitors of every step (the per-step scalar set of
+ * the stepping path): mon_steps[i] (device array of n_steps structs) receives
+ * the monitors of the state after step i + 1 -- alpha range, field
+ * integrals, non-physical count, max |P - p_ref|, max |u - u_ref| -- and the
+ * time-step rate of that state with its dt (the step that would follow;
+ * *dt_fixed when given).  The last stage of each step emits the records that
+ * one two-level reduction per step turns into these monitors and the next
+ * dt.  Same states and dt as dg2p_advance.  A NaN anywhere in a state's rate
+ * or monitors propagates (the dt of a state with a failed closure is NaN).
+ * work: dg2p_workspace_size(DG2P_OP_ADVANCE) bytes. */
+int dg2p_advance_monitored(dg2p_mesh m, const dg2p_params* p /*host*/, double* U /*device, in/out*/, int n_steps,
+                           double cfl, const double* dt_fixed /*device, nullable*/, double* t /*device, nullable*/,
+                           double* dt_last /*device, nullable*/, dg2p_monitors* mon_steps /*device [n_steps]*/,
+                           double p_ref, const double* u_ref /*host, nullable*/, void* work /*device*/,
+                           void* stream);
 
 /* Vector-Jacobian product of dg2p_rhs (hand-written reverse mode):
  * U_bar = (dR/dU)^T R_bar, overwritten; if param_bar != NULL,

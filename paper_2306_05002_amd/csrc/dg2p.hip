@@ -764,37 +764,40 @@ int dg2p_rk_step_noalloc(dg2p_mesh m, const dg2p_params* p, double* U, const dou
 
 size_t dg2p_noalloc_scratch_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
 
-int dg2p_advance(dg2p_mesh m, const dg2p_params* p, double* U, int n_steps, double cfl, const double* dt_fixed,
-                 double* t, double* dt_last, dg2p_monitors* mon, double p_ref, const double* u_ref, void* work,
-                 void* stream) {
-  g_last_error.clear();
-  if (!m || !U) return fail(DG2P_EINVAL, "mesh and U must be non-NULL");
-  if (n_steps < 0) return fail(DG2P_EINVAL, "n_steps must be >= 0");
-  if (!dt_fixed && !(cfl > 0.0)) return fail(DG2P_EINVAL, "cfl must be > 0");
-  int st = check_params(m, p);
-  if (st) return st;
-  st = check_ws(work, work_bytes(m, p, DG2P_OP_ADVANCE));
-  if (st) return st;
+}  // extern "C"
+
+namespace {
+
+// n_steps SSP-RK3 steps in place.  Without per-step monitors (mon_steps ==
+// NULL) the last stage of every step writes 2-double rate records, from which
+// the next step's dt is reduced inside its first stage (small grids) or by
+// two small kernels; with them, the last stage writes the full 16-slot
+// records and one reduction per step yields the step's monitors and the next
+// dt.
+int advance_impl(const dg2p_mesh_s* m, const dg2p_params* p, double* U, int n_steps, double cfl,
+                 const double* dt_fixed, double* t, double* dt_last, dg2p_monitors* mon, dg2p_monitors* mon_steps,
+                 double p_ref, const double* u_ref, void* work, hipStream_t s) {
   KArgs A = make_args(m, p);
   A.p_ref = p_ref;
   if (u_ref)
     for (int k = 0; k < m->dim; ++k) A.u_ref[k] = u_ref[k];
   Work w = carve(m, p, DG2P_OP_ADVANCE, work);
-  hipStream_t s = (hipStream_t)stream;
   double* dts = dt_last ? dt_last : w.dt;
   double* Ga = w.G0;
   double* Gb = w.G1;
-  // rate records (2 doubles per workgroup) of the ingredient pass and of
-  // every step's last stage; the next step's dt is reduced from them either
-  // inside its first stage (small grids) or by two small kernels
-  const long long nrate = elem_blocks(m);
-  const bool fused = nrate <= FUSED_DT_MAX;
+  // records (rate-only or full) of the ingredient pass and of every step's
+  // last stage, one per workgroup
+  const long long nrec = elem_blocks(m);
+  const bool fused = !mon_steps && nrec <= FUSED_DT_MAX;
   A.cfl = cfl;
   A.hmin = min_h(m);
-  A.nrate = nrate;
+  A.nrate = nrec;
   launch_ingr(m, p, A, U, Ga, w.rec, s);
   for (int it = 0; it < n_steps; ++it) {
-    if (!fused) finalize_rate(m, A, w, nrate, cfl, dt_fixed, dts, t, s);
+    if (mon_steps && it > 0)
+      finalize(m, A, w, nrec, cfl, dt_fixed, dts, t, mon_steps + (it - 1), s);
+    else if (!fused)
+      finalize_rate(m, A, w, nrec, cfl, dt_fixed, dts, t, s);
     KArgs B = A;
     StageIO io1{U, Ga, nullptr, w.U1, Gb, nullptr, dts};
     if (fused) {
@@ -811,17 +814,54 @@ int dg2p_advance(dg2p_mesh m, const dg2p_params* p, double* U, int n_steps, doub
     B.rk_a = 1.0 / 3.0;
     B.rk_b = 2.0 / 3.0;
     StageIO io3{w.U2, Ga, U, U, Gb, w.rec, dts};
-    launch_stage(m, p, 2, 3, B, io3, s);
+    launch_stage(m, p, 2, mon_steps ? 2 : 3, B, io3, s);
     double* tmp = Ga;
     Ga = Gb;
     Gb = tmp;
   }
+  if (mon_steps && n_steps > 0)
+    finalize(m, A, w, nrec, cfl, dt_fixed, nullptr, nullptr, mon_steps + (n_steps - 1), s);
   if (mon) {
-    // monitors of the final state (the per-step records carry the rate only)
+    // monitors of the final state
     launch_records(m, p, A, U, w.rec, s);
     finalize(m, A, w, records_of_records(m, p, 1), cfl, nullptr, nullptr, nullptr, mon, s);
   }
   return hip_check(hipGetLastError(), "advance launch");
+}
+
+int advance_checks(const dg2p_mesh_s* m, const dg2p_params* p, double* U, int n_steps, double cfl,
+                   const double* dt_fixed, void* work) {
+  if (!m || !U) return fail(DG2P_EINVAL, "mesh and U must be non-NULL");
+  if (n_steps < 0) return fail(DG2P_EINVAL, "n_steps must be >= 0");
+  if (!dt_fixed && !(cfl > 0.0)) return fail(DG2P_EINVAL, "cfl must be > 0");
+  int st = check_params(m, p);
+  if (st) return st;
+  return check_ws(work, work_bytes(m, p, DG2P_OP_ADVANCE));
+}
+
+}  // namespace
+
+extern "C" {
+
+int dg2p_advance(dg2p_mesh m, const dg2p_params* p, double* U, int n_steps, double cfl, const double* dt_fixed,
+                 double* t, double* dt_last, dg2p_monitors* mon, double p_ref, const double* u_ref, void* work,
+                 void* stream) {
+  g_last_error.clear();
+  int st = advance_checks(m, p, U, n_steps, cfl, dt_fixed, work);
+  if (st) return st;
+  return advance_impl(m, p, U, n_steps, cfl, dt_fixed, t, dt_last, mon, nullptr, p_ref, u_ref, work,
+                      (hipStream_t)stream);
+}
+
+int dg2p_advance_monitored(dg2p_mesh m, const dg2p_params* p, double* U, int n_steps, double cfl,
+                           const double* dt_fixed, double* t, double* dt_last, dg2p_monitors* mon_steps,
+                           double p_ref, const double* u_ref, void* work, void* stream) {
+  g_last_error.clear();
+  if (!mon_steps) return fail(DG2P_EINVAL, "mon_steps must be non-NULL");
+  int st = advance_checks(m, p, U, n_steps, cfl, dt_fixed, work);
+  if (st) return st;
+  return advance_impl(m, p, U, n_steps, cfl, dt_fixed, t, dt_last, nullptr, mon_steps, p_ref, u_ref, work,
+                      (hipStream_t)stream);
 }
 
 int dg2p_compute_monitors(dg2p_mesh m, const dg2p_params* p, const double* U, double p_ref, const double* u_ref,

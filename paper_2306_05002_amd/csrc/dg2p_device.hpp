@@ -487,14 +487,21 @@ __device__ __forceinline__ void gradients(const KArgs& A, const double* q, const
 }
 
 // ---- reduction helpers -----------------------------------------------------------
+// Maximum and minimum that propagate NaN (fmax / fmin drop it): a node whose
+// closure fails (e.g. a negative squared sound speed) turns the reduced rate,
+// hence dt, and the reduced monitors into NaN, as the oracle's reductions do,
+// instead of being skipped.  Exact and order-independent, like fmax.
+__device__ __forceinline__ double nan_max(double a, double b) { return (a > b || a != a) ? a : b; }
+__device__ __forceinline__ double nan_min(double a, double b) { return (a < b || a != a) ? a : b; }
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  for (int o = 32; o >= 1; o >>= 1) v = nan_max(v, __shfl_xor(v, o));
   return v;
 }
 __device__ __forceinline__ double wave_min(double v) {
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  for (int o = 32; o >= 1; o >>= 1) v = nan_min(v, __shfl_xor(v, o));
   return v;
 }
 __device__ __forceinline__ double wave_sum(double v) {
@@ -519,7 +526,7 @@ __device__ __forceinline__ void block_rate_record(double w, double nu, double* r
     const int s = threadIdx.x;  // R_WAVE, R_NU
     double x = sh[s][0];
 #pragma unroll
-    for (int i = 1; i < BLOCK / 64; ++i) x = fmax(x, sh[s][i]);
+    for (int i = 1; i < BLOCK / 64; ++i) x = nan_max(x, sh[s][i]);
     rec[blk * RATE + s] = x;
   }
 }
@@ -527,7 +534,7 @@ __device__ __forceinline__ void block_rate_record(double w, double nu, double* r
 // Time-step rule from the reduced maxima: rate = (max wave + (p+1)^2 d
 // nu_max / h_min) / h_min with nu_max = max(Gamma eps, max mu/rho).
 __device__ __forceinline__ double rate_of(double wmax, double numax, double GammaEps, int dim, double hmin) {
-  const double nu = fmax(GammaEps, numax);
+  const double nu = nan_max(GammaEps, numax);
   return (wmax + 16.0 * dim * nu / hmin) / hmin;
 }
 
@@ -554,8 +561,8 @@ __device__ __forceinline__ void fused_dt_load(const KArgs& A, const double* __re
 #pragma unroll
   for (int u = 0; u < FUSED_RATE_PER_THREAD; ++u) {
     const bool ok = threadIdx.x + u * BLOCK < A.nrate;
-    w = fmax(w, ok ? vw[u] : 0.0);
-    nu = fmax(nu, ok ? vn[u] : 0.0);
+    w = nan_max(w, ok ? vw[u] : 0.0);
+    nu = nan_max(nu, ok ? vn[u] : 0.0);
   }
   w = wave_max(w);
   nu = wave_max(nu);
@@ -574,8 +581,8 @@ __device__ __forceinline__ double fused_dt_finish(const KArgs& A, double (*sh)[B
   double nu = sh[1][0];
 #pragma unroll
   for (int i = 1; i < BLOCK / 64; ++i) {
-    w = fmax(w, sh[0][i]);
-    nu = fmax(nu, sh[1][i]);
+    w = nan_max(w, sh[0][i]);
+    nu = nan_max(nu, sh[1][i]);
   }
   return A.cfl / rate_of(w, nu, A.GammaEps, dim, A.hmin);
 }
@@ -597,7 +604,7 @@ __device__ __forceinline__ void node_record(const KArgs& A, const double* q, con
                    !isfinite(p.P) || !isfinite(p.c);
   double du = 0.0;
 #pragma unroll
-  for (int j = 0; j < DIM; ++j) du = fmax(du, fabs(p.u[j] - A.u_ref[j]));
+  for (int j = 0; j < DIM; ++j) du = nan_max(du, fabs(p.u[j] - A.u_ref[j]));
   double W = 1.0;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
@@ -616,8 +623,8 @@ __device__ __forceinline__ void node_record(const KArgs& A, const double* q, con
 }
 
 __device__ __forceinline__ double rec_combine(int slot, double a, double b) {
-  if (slot == R_AMIN) return fmin(a, b);
-  if (slot == R_WAVE || slot == R_NU || slot == R_AMAX || slot == R_DEVP || slot == R_DEVU) return fmax(a, b);
+  if (slot == R_AMIN) return nan_min(a, b);
+  if (slot == R_WAVE || slot == R_NU || slot == R_AMAX || slot == R_DEVP || slot == R_DEVU) return nan_max(a, b);
   return a + b;
 }
 __device__ __forceinline__ double rec_wave(int slot, double v) {
@@ -639,13 +646,13 @@ __device__ __forceinline__ void rs_step(double* v, int m, bool upper) {
     const double send = upper ? lo : hi;
     const double keep = upper ? hi : lo;
     const double got = __shfl_xor(send, m);
-    v[i] = OP == 0 ? keep + got : fmax(keep, got);
+    v[i] = OP == 0 ? keep + got : nan_max(keep, got);
   }
 }
 template <int OP>
 __device__ __forceinline__ double bfly(double x, int m) {
   const double got = __shfl_xor(x, m);
-  return OP == 0 ? x + got : fmax(x, got);
+  return OP == 0 ? x + got : nan_max(x, got);
 }
 template <int NS, int OP>
 __device__ __forceinline__ double wave_reduce_scatter(double* v) {

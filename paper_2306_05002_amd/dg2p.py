@@ -78,6 +78,8 @@ _SIG = {
     "dg2p_noalloc_scratch_bytes": ([], ctypes.c_size_t),
     "dg2p_compute_monitors": ([_vp, ctypes.POINTER(Params), _dp, _d, _dp, _vp, _vp, _vp], _i),
     "dg2p_advance": ([_vp, ctypes.POINTER(Params), _dp, _i, _d, _dp, _dp, _dp, _vp, _d, _vp, _vp, _vp], _i),
+    "dg2p_advance_monitored": ([_vp, ctypes.POINTER(Params), _dp, _i, _d, _dp, _dp, _dp, _vp, _d, _vp, _vp,
+                                _vp], _i),
     "dg2p_rhs_vjp": ([_vp, ctypes.POINTER(Params), _dp, _dp, _dp, _dp, _vp, _vp], _i),
     "dg2p_rk_step_vjp": ([_vp, ctypes.POINTER(Params), _dp, _dp, _dp, _dp, _dp, _vp, _vp], _i),
     "dg2p_prim_to_cons_vjp": ([_vp, ctypes.POINTER(Params), _dp, _dp, _dp, _vp], _i),
@@ -303,6 +305,24 @@ def advance(mesh, params, U, n_steps, cfl=0.1, dt_fixed=None, t=None, dt_last=No
     return U
 
 
+def advance_monitored(mesh, params, U, n_steps, mon_steps, cfl=0.1, dt_fixed=None, t=None, dt_last=None,
+                      p_ref=0.0, u_ref=None, stream=None):
+    """advance() with the monitors of every step: mon_steps is a float64
+    device tensor of shape (n_steps, MONITOR_DOUBLES); row i receives the
+    monitors of the state after step i + 1 (decode with decode_monitors)."""
+    U = _as_state(mesh, U)
+    if (mon_steps.dtype != torch.float64 or not mon_steps.is_cuda or not mon_steps.is_contiguous()
+            or mon_steps.numel() < int(n_steps) * MONITOR_DOUBLES):
+        raise ValueError("mon_steps must be a contiguous float64 CUDA tensor of n_steps x MONITOR_DOUBLES")
+    ws = mesh.workspace(params, OP_ADVANCE, U.device)
+    ur = (ctypes.c_double * 3)(*([0.0, 0.0, 0.0] if u_ref is None else (list(u_ref) + [0.0] * 3)[:3]))
+    _check(_lib.dg2p_advance_monitored(mesh.handle, ctypes.byref(params), _ptr(U), int(n_steps), float(cfl),
+                                       _ptr(dt_fixed), _ptr(t), _ptr(dt_last), _ptr(mon_steps), float(p_ref),
+                                       ctypes.cast(ur, ctypes.c_void_p), ws, _stream(stream)),
+           "dg2p_advance_monitored")
+    return U
+
+
 def rhs_vjp(mesh, params, U, R_bar, param_bar=None, stream=None):
     """U_bar = (dR/dU)^T R_bar; param_bar (1-element device tensor) += sigma cotangent."""
     U = _as_state(mesh, U)
@@ -326,7 +346,11 @@ def rk_step_vjp(mesh, params, U_n, dt, U_np1_bar, param_bar=None, out=None, stre
 
 
 def decode_monitors(buf, nf):
+    """Monitors from a device or host buffer of MONITOR_DOUBLES float64 (a
+    dg2p_monitors struct); for a (n, MONITOR_DOUBLES) buffer, a list of n."""
     raw = buf.detach().cpu().numpy()
+    if raw.ndim == 2:
+        return [decode_monitors(torch.from_numpy(r.copy()), nf) for r in raw]
     m = Monitors.from_buffer_copy(raw.tobytes())
     return dict(max_rate=m.max_rate, dt=m.dt, min_alpha=m.min_alpha, max_alpha=m.max_alpha,
                 integral=list(m.integral)[:nf], dev_p=m.dev_p, dev_u=m.dev_u,

@@ -157,7 +157,7 @@ def config(name, n_elem=None):
     return cfg
 
 
-def _rt_interface_noise(x, y):
+def _rt_interface_noise(x, y, scaled=True):
     """Seeded 1e-3 perturbation of the Rayleigh-Taylor interface: 4 x 4 Fourier
     modes with N(0,1) amplitudes (seed 3), scaled to max |zeta| = 1 on a 256^2
     grid.  Separable form: cos/sin of 2 pi (m x + n y) from the per-axis
@@ -179,10 +179,52 @@ def _rt_interface_noise(x, y):
                 z += A[m, n] * c + B[m, n] * s_
         return z
 
+    if not scaled:
+        return zeta(x, y)
     g = (np.arange(256) + 0.5) / 256.0
     gx, gy = np.meshgrid(g, g, indexing="ij")
     scale = np.abs(zeta(gx, gy)).max()
     return zeta(x, y) / scale
+
+
+def _rt3d_fields(X, eps, r1, r2, d, shp):
+    """rt3d: interface z = eta(x, y) = 0.5 + 0.02 cos 2 pi x cos 2 pi y + 1e-3 zeta,
+    psi = eta - z, hydrostatic P for g = -e_z with P(z = 1) = 1:
+    P = 1 + int_z^1 rho dz' with rho = rho2 + (rho1 - rho2) alpha."""
+    import torch
+    x, y, z = (torch.from_numpy(np.ascontiguousarray(X[k])) for k in range(3))
+    eta = (0.5 + 0.02 * torch.cos(2 * math.pi * x) * torch.cos(2 * math.pi * y)
+           + 1e-3 * torch.from_numpy(_rt_interface_noise_t(x, y)))
+    psi = eta - z
+    def sp(t):  # softplus log(1 + e^t) without torch's large-argument cut-off
+        return torch.clamp(t, min=0.0) + torch.log1p(torch.exp(-torch.abs(t)))
+
+    P = 1.0 + r2 * (1.0 - z) + (r1 - r2) * eps * (sp((eta - z) / eps) - sp((eta - 1.0) / eps))
+    alpha = torch.sigmoid(psi / eps)
+    return dict(alpha=alpha.numpy(), psi=psi.numpy(), rho1=np.full(shp, r1), rho2=np.full(shp, r2),
+                P=P.numpy(), u=np.zeros((d,) + shp))
+
+
+def _rt_interface_noise_t(x, y):
+    """_rt_interface_noise on torch CPU tensors (same modes and scale)."""
+    import torch
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((4, 4))
+    B = rng.standard_normal((4, 4))
+    g = (np.arange(256) + 0.5) / 256.0
+    gx, gy = np.meshgrid(g, g, indexing="ij")
+    scale = np.abs(_rt_interface_noise(gx, gy, scaled=False)).max()
+    cx = [torch.cos(2.0 * math.pi * m * x) for m in range(1, 5)]
+    sx = [torch.sin(2.0 * math.pi * m * x) for m in range(1, 5)]
+    cy = [torch.cos(2.0 * math.pi * n * y) for n in range(1, 5)]
+    sy = [torch.sin(2.0 * math.pi * n * y) for n in range(1, 5)]
+    zt = torch.zeros_like(x)
+    for m in range(4):
+        # sum_n A_mn cos 2 pi (m x + n y) + B_mn sin 2 pi (m x + n y)
+        cm = sum(float(A[m, n]) * cy[n] + float(B[m, n]) * sy[n] for n in range(4))
+        sm = sum(float(B[m, n]) * cy[n] - float(A[m, n]) * sy[n] for n in range(4))
+        zt += cx[m] * cm + sx[m] * sm
+    return (zt / scale).numpy()
 
 
 def primitive_fields(cfg, coords, variant=None):
@@ -244,14 +286,9 @@ def primitive_fields(cfg, coords, variant=None):
         P = (cfg["p_top"] + r2 * (top - y)
              + (r1 - r2) * eps * (_softplus((eta - y) / eps) - _softplus((eta - top) / eps)))
     elif name == "rt3d":
-        x, y, z = X[0], X[1], X[2]
-        eta = (0.5 + 0.02 * np.cos(2 * math.pi * x) * np.cos(2 * math.pi * y)
-               + 1e-3 * _rt_interface_noise(x, y))
-        psi = eta - z
-        # hydrostatic column for g = -e_z, P(z=1) = 1:
-        # P = 1 + int_z^1 rho dz' with rho = rho2 + (rho1 - rho2) alpha
-        P = (1.0 + r2 * (1.0 - z)
-             + (r1 - r2) * eps * (_softplus((eta - z) / eps) - _softplus((eta - 1.0) / eps)))
+        # evaluated with torch's multithreaded CPU kernels (the 96^3 box has
+        # 56.6 M nodes); the formulas are those of the other cases
+        return _rt3d_fields(X, eps, r1, r2, d, shp)
     else:
         raise KeyError(name)
     alpha = _sigmoid(psi / eps)
