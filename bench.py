@@ -1,10 +1,13 @@
 #!/usr/bin/env python3
 """Benchmark: DOF-updates/s of the DG SSP-RK3 stage on one MI355X.
 
-One step = one pass of the whole hot path on the workload: the time-step
-reduction of the step's state (device scalar dt) and one SSP-RK3 step (three
-residual + stage-combine passes), run by dg2p_advance with the state resident
-in HBM and no host synchronisation inside the timed region.
+Headline workload: the 3D heavy-over-light box, 96^3 hexahedra, p = 3,
+viscous + CSF + gravity, FP64 (the largest configuration; 3.6 GB per state,
+so every stage streams its arrays through HBM).  One step = one pass of the
+whole hot path: SSP-RK3's three residual + stage-combine passes, the
+time-step reduction and the per-step monitors (alpha range, field integrals,
+non-physical count, P/u deviations), run by dg2p_advance_monitored with the
+state resident in HBM and no host synchronisation inside the timed region.
 value = 3 * N_nodes * N_fields / (seconds per step).
 
 The JSON line also carries
@@ -13,11 +16,19 @@ The JSON line also carries
                 U^n and writes U^1, stages 2 and 3 read U^n and U^s and write
                 U^{s+1}) divided by its mean launch duration, measured with
                 hipEvents the library records around its own launches on the
-                launch stream; HBM peak 8 TB/s.  `traffic` is the counter-
-                measured HBM traffic per launch recorded under profiles/ for
-                the current kernel sources (null if the sources changed).
-  cpu_baseline: the FP64 CPU oracle's residual evaluations on the host cores
-                over a bounded sample of the same workload.
+                launch stream during the timed region; HBM peak 8 TB/s.
+                `traffic` is the counter-measured HBM traffic per launch
+                recorded under profiles/ for the current kernel sources (null
+                if the sources changed since).
+  mixed_precision: FP32 and BF16 contraction forms on the 512 x 256 shock
+                (200 steps) and the 96^3 box (100 steps): per-field L2 / Linf
+                error against the FP64 path and speed.
+  cache_resident_2d: the 128^2 droplet (its ~60 MB working set stays in the
+                256 MB Infinity Cache, so its fraction is fabric bandwidth,
+                not HBM).
+  cpu_baseline: the FP64 CPU oracle's residual on a bounded sample of the
+                headline workload, with one thread and with every core of the
+                host (core count from os.sched_getaffinity).
 
 --gpus N with N > 1 is refused: this build runs on one GPU.
 """
@@ -50,6 +61,9 @@ WORKLOAD_DESC = {
 # enough for the clocks to settle and the event timing to be stable
 DEFAULT_STEPS = {"drop1d": 2000, "drop2d": 1000, "shock2d": 200, "rt3d": 20, "adjoint2d": 1000,
                  "waterair2d": 2000, "bubble2d": 2000, "rt2d": 1000}
+HEADLINE = "rt3d"
+# workloads whose working set exceeds the 256 MB Infinity Cache (HBM-bound)
+HBM_RESIDENT = {"shock2d", "rt3d"}
 
 
 def source_hash():
@@ -85,8 +99,9 @@ def recorded(workload, what, key, src_hash):
 VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4
 
 
-def cpu_baseline(cfg, seconds):
-    """FP64 oracle residual evaluations on the host, bounded to ~`seconds`."""
+def oracle_state(cfg, pf):
+    """The oracle's mesh, parameters and initial state from the primitive
+    fields (the oracle's own initial-condition map)."""
     import numpy as np
     import torch
     import oracle
@@ -101,28 +116,43 @@ def cpu_baseline(cfg, seconds):
                                  t(bp["P"]), prm)
         bc_state[key] = Qb[:, 0]
     om = oracle.OracleMesh(d, cfg["order"], cfg["n_elem"], cfg["lo"], cfg["hi"], cfg["bc"], bc_state)
-    # bounded sample: at most 16384 elements (the whole grid when it is smaller)
-    n_s = min(om.E, 16384)
-    el = torch.arange(n_s)
-    from paper_2306_05002_amd import workloads
-    X = om.node_coords()
-    pf = workloads.primitive_fields(cfg, X.numpy())
     T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64)
     U = oracle.prim_to_cons(T(pf["alpha"]), T(pf["psi"]), T(pf["rho1"]), T(pf["rho2"]),
                             T(pf["u"]), T(pf["P"]), prm)
-    oracle.rhs(U, om, prm, elems=el)
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        oracle.rhs(U, om, prm, elems=el)
-        reps += 1
-        el_t = time.perf_counter() - t0
-        if el_t >= seconds or reps >= 200:
-            break
+    return om, prm, U
+
+
+def cpu_baseline(cfg, pf, seconds):
+    """FP64 oracle residual evaluations on the host over a bounded sample of
+    the workload (at most 4096 consecutive elements from the middle of the
+    grid, whose faces reach into the rest of it), about `seconds` per thread
+    count, with one thread and with every core the process may run on."""
+    import torch
+    import oracle
+
+    om, prm, U = oracle_state(cfg, pf)
+    n_s = min(om.E, 4096)
+    lo = (om.E - n_s) // 2
+    el = torch.arange(lo, lo + n_s)
+    cores = len(os.sched_getaffinity(0))
     dof = n_s * om.nn * om.nf
-    sample = (f"oracle residual (one RK stage's work) on {n_s} of {om.E} elements, "
-              f"{reps} evaluations, {el_t:.1f} s")
-    return dict(value=dof * reps / el_t, unit="DOF-updates/s", cores=torch.get_num_threads(),
-                kind="oracle", sample=sample)
+    rates = {}
+    for nt in (1, cores):
+        torch.set_num_threads(nt)
+        oracle.rhs(U, om, prm, elems=el)
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            oracle.rhs(U, om, prm, elems=el)
+            reps += 1
+            el_t = time.perf_counter() - t0
+            if el_t >= seconds or reps >= 200:
+                break
+        rates[nt] = (dof * reps / el_t, reps, el_t)
+    sample = (f"oracle residual (one RK stage's work) on elements {lo}..{lo + n_s - 1} of {om.E}; "
+              f"{rates[cores][1]} evaluations in {rates[cores][2]:.1f} s with {cores} threads, "
+              f"{rates[1][1]} in {rates[1][2]:.1f} s with 1 thread")
+    return dict(value=rates[cores][0], unit="DOF-updates/s", cores=cores, kind="oracle", sample=sample,
+                value_1_thread=rates[1][0], threads=[1, cores])
 
 
 # L1 errors of the paper's Rider-Kothe table (quadrilateral mesh, p = 3) at
@@ -293,20 +323,208 @@ def calibrate_copy(gib=2.0, reps=10):
     print(json.dumps({"calibration": "copy", "bytes_read": n * 8, "bytes_written": n * 8, "launches": reps}))
 
 
+def initial_state(cfg, mesh, P):
+    """Primitive fields of the workload at the mesh's nodes (host) and the
+    conserved initial state on the GPU (the library's initial-condition map)."""
+    from paper_2306_05002_amd import dg2p, workloads
+    pf = workloads.primitive_fields(cfg, mesh.node_coords())
+    U0 = dg2p.prim_to_cons(mesh, P, dg2p.prim_tensor(pf, cfg["dim"]))
+    return pf, U0
+
+
+def stage_timing(dg2p, n_steps, ms_step):
+    """Per-launch means of the kernel kinds recorded by the library while its
+    timing was enabled, and the stage kernel's mean."""
+    k_ms = {}
+    for name, kind in (("stage", dg2p.K_STAGE), ("ingredients", dg2p.K_INGREDIENTS),
+                       ("rate", dg2p.K_RATE), ("rate_final", dg2p.K_RATE_FINAL)):
+        k_ms[name] = dg2p.timing_read(kind)
+    # the step less the other kernels' share, over its three stage launches
+    other = sum(k_ms[k][0] * k_ms[k][1] for k in ("ingredients", "rate", "rate_final")) / n_steps
+    return k_ms, (ms_step - other) / 3.0
+
+
+def timed_steps(mesh, P, U, steps, warmup, cfl, monitored=True, events=False):
+    """warmup untimed steps, then `steps` timed steps (CUDA events around the
+    batch on the current stream; with events=True the library also records
+    its per-launch hipEvents during the timed batch).  Returns ms per step,
+    the per-step monitors of the timed steps (or None) and the wall time."""
+    import torch
+    from paper_2306_05002_amd import dg2p
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+    ms = torch.zeros(max(steps, warmup, 1), dg2p.MONITOR_DOUBLES, dtype=torch.float64, device="cuda")
+
+    def run(n):
+        if monitored:
+            dg2p.advance_monitored(mesh, P, U, n, ms, cfl=cfl, t=t, dt_last=dt, p_ref=1.0)
+        else:
+            dg2p.advance(mesh, P, U, n, cfl=cfl, t=t, dt_last=dt)
+
+    run(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    if events:
+        dg2p.timing_enable(True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    run(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if events:
+        dg2p.timing_enable(False)
+    mon = dg2p.decode_monitors(ms[:steps], mesh.nf) if monitored else None
+    return e0.elapsed_time(e1) / steps, mon, wall
+
+
+def roofline(workload, dof, stage_ms, event_ms, src):
+    alg_bytes = (64.0 / 3.0) * dof          # per stage launch, averaged over the 3 stages
+    achieved = alg_bytes / (event_ms * 1e-3) / 1e9
+    traffic = recorded(workload, "traffic", "traffic_bytes_per_launch", src)
+    valu = recorded(workload, "valu", "valu_insts_per_launch", src)
+    return {
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": traffic,
+        "kernel": "k_stage (residual + stage combine)",
+        "kernel_mean_ms": event_ms,
+        "kernel_mean_ms_from_step": stage_ms,
+        "valu_issue": None if valu is None else {
+            "insts_per_launch": valu,
+            "issue_ms": valu / VALU_ISSUE_PER_S * 1e3,
+            "frac": valu / VALU_ISSUE_PER_S * 1e3 / event_ms},
+        "algorithmic_bytes_per_launch": alg_bytes,
+    }
+
+
+def mixed_section(name, U0=None, mesh=None, steps=20, warmup=5, cfl=0.1):
+    """FP32 and BF16 contraction forms of one workload: per-field error
+    against the FP64 path after the workload's error horizon (same initial
+    state, same fixed dt: that of the initial state) and speed."""
+    import torch
+    from paper_2306_05002_amd import dg2p, workloads
+    cfg = workloads.config(name)
+    P64 = dg2p.make_params(cfg["params"])
+    if mesh is None:
+        mesh = dg2p.mesh_from_config(cfg, P64)
+        U0 = initial_state(cfg, mesh, P64)[1]
+    dof = mesh.E * mesh.nn * mesh.nf
+    n_err = ERROR_STEPS[name]
+    dt0 = dg2p.max_dt(mesh, P64, U0, cfl=cfl)
+    Uref = U0.clone()
+    dg2p.advance(mesh, P64, Uref, n_err, dt_fixed=dt0)
+    Wn = torch.from_numpy(mesh.node_weights()).cuda()
+    out = {"workload": f"{name}: {WORKLOAD_DESC[name]}", "error_steps": n_err,
+           "error_reference": "FP64 GPU path (itself within 1e-12 of the oracle), same fixed dt"}
+    U = U0.clone()
+    ms64, _, _ = timed_steps(mesh, P64, U, steps, warmup, cfl, monitored=True)
+    out["fp64"] = {"value": 3.0 * dof / (ms64 * 1e-3), "ms_per_step": ms64}
+    for prec in ("fp32", "bf16"):
+        Pm = dg2p.make_params(cfg["params"], precision=prec)
+        Ue = U0.clone()
+        dg2p.advance(mesh, Pm, Ue, n_err, dt_fixed=dt0)
+        err = field_errors(Ue, Uref, Wn, cfg["dim"], n_err)
+        m = dg2p.monitors(mesh, P64, Ue)
+        del Ue
+        U = U0.clone()
+        msm, _, _ = timed_steps(mesh, Pm, U, steps, warmup, cfl, monitored=True)
+        out[prec] = {"error_vs_fp64": err, "nonphys_after": m["nonphys"],
+                     "value": 3.0 * dof / (msm * 1e-3), "ms_per_step": msm, "speedup_vs_fp64": ms64 / msm,
+                     "contractions": prec, "closure_and_rk": "fp64"}
+    del Uref, U
+    return out
+
+
+def cache_resident_section(src, cfl=0.1):
+    """The 128 x 128 droplet (FP64): its ~60 MB working set stays in the
+    Infinity Cache, so the bandwidth figure is fabric traffic, not HBM."""
+    from paper_2306_05002_amd import dg2p, workloads
+    name = "drop2d"
+    cfg = workloads.config(name)
+    P = dg2p.make_params(cfg["params"])
+    mesh = dg2p.mesh_from_config(cfg, P)
+    U = initial_state(cfg, mesh, P)[1]
+    dof = mesh.E * mesh.nn * mesh.nf
+    steps = DEFAULT_STEPS[name]
+    msd, _, _ = timed_steps(mesh, P, U, steps, steps // 4, cfl, monitored=False)
+    ms_mon, _, _ = timed_steps(mesh, P, U, steps, steps // 4, cfl, monitored=True, events=True)
+    k_ms, stage_ms = stage_timing(dg2p, steps, ms_mon)
+    rl = roofline(name, dof, stage_ms, stage_ms, src)
+    rl["bound"] = "infinity-cache resident (fabric, not HBM)"
+    return {"workload": f"{name}: {WORKLOAD_DESC[name]}", "value": 3.0 * dof / (msd * 1e-3),
+            "ms_per_step": msd, "step": "dg2p_advance (dt fused into the first stage, no per-step monitors)",
+            "value_with_step_monitors": 3.0 * dof / (ms_mon * 1e-3), "ms_per_step_with_step_monitors": ms_mon,
+            "roofline_cache": rl}
+
+
+def adjoint_section(steps):
+    """VJP of one SSP-RK3 step on the adjoint workload (viscous + CSF droplet,
+    128 x 128, frozen dt), and central-difference agreement of the gradient
+    of the 400-step rollout."""
+    import torch
+    from paper_2306_05002_amd import dg2p
+    from paper_2306_05002_amd import adjoint as adj
+    prob = adj.AdjointProblem()
+    Ua = dg2p.prim_to_cons(prob.mesh, prob.P, prob.prim0)
+    Wb = torch.randn(Ua.shape, dtype=torch.float64, device="cuda",
+                     generator=torch.Generator(device="cuda").manual_seed(0))
+    Ub = torch.empty_like(Ua)
+    sb = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        dg2p.rk_step_vjp(prob.mesh, prob.P, Ua, prob.dt, Wb, param_bar=sb, out=Ub)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    n_adj = max(5, min(steps, 50))
+    e0.record(stream)
+    for _ in range(n_adj):
+        dg2p.rk_step_vjp(prob.mesh, prob.P, Ua, prob.dt, Wb, param_bar=sb, out=Ub)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_vjp = e0.elapsed_time(e1) / n_adj
+    dof_a = prob.mesh.E * prob.mesh.nn * prob.mesh.nf
+    L0, gu, gs = prob.gradient()
+    worst = 0.0
+    h = 1e-6
+    for k in range(16):
+        du, ds = prob.fd_directions(k)
+        with torch.no_grad():
+            Lp = float(prob.loss(prob.u0 + h * du, prob.sigma0 + h * ds))
+            Lm = float(prob.loss(prob.u0 - h * du, prob.sigma0 - h * ds))
+        fd = (Lp - Lm) / (2 * h)
+        ad = float((gu * du).sum()) + gs * ds
+        worst = max(worst, abs(fd - ad) / max(abs(fd), abs(ad), 1e-300))
+    return {"workload": "adjoint2d: droplet 128x128 p=3, viscous + CSF, 400 steps, checkpoint every 20",
+            "value": 3.0 * dof_a / (ms_vjp * 1e-3), "unit": "DOF-updates/s",
+            "ms_per_step_vjp": ms_vjp,
+            "step_vjp": "recompute 2 stages + 3 residual VJPs (local + gather)",
+            "fd_directions": 16, "fd_step": h, "fd_max_rel_err": worst,
+            "dL_dsigma": gs}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default: about 50 ms of GPU time for the workload)")
+                    help="timed steps (default: about 50 ms of GPU time for the workload, 20 on the 96^3 box)")
     ap.add_argument("--warmup", type=int, default=None,
-                    help="untimed steps before the timed region (default: a quarter of --steps)")
-    ap.add_argument("--workload", default="drop2d", choices=sorted(WORKLOAD_DESC))
+                    help="untimed steps before the timed region (default: a quarter of --steps, at least 10)")
+    ap.add_argument("--workload", default=HEADLINE, choices=sorted(WORKLOAD_DESC))
     ap.add_argument("--cfl", type=float, default=0.1)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="oracle timing per thread count (one thread, then every core)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip the mixed-precision, adjoint and kinematic measurements")
+                    help="skip the mixed-precision, cache-resident, adjoint, kinematic, water-air and "
+                         "wall-bounded measurements")
     args = ap.parse_args()
     if args.steps is None:
         args.steps = DEFAULT_STEPS[args.workload]
@@ -327,144 +545,52 @@ def main():
     cfg = workloads.config(args.workload)
     P = dg2p.make_params(cfg["params"])
     mesh = dg2p.mesh_from_config(cfg, P)
-    pf = workloads.primitive_fields(cfg, mesh.node_coords())
-    U = dg2p.prim_to_cons(mesh, P, dg2p.prim_tensor(pf, cfg["dim"]))
-    del pf
-    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+    pf, U0 = initial_state(cfg, mesh, P)
+    U = U0.clone()
     n_nodes = mesh.E * mesh.nn
     dof = n_nodes * mesh.nf
-
-    tsim = torch.zeros(1, dtype=torch.float64, device="cuda")
-
-    def steps(n):
-        # n SSP-RK3 steps; each step's dt reduced on the device from its state
-        dg2p.advance(mesh, P, U, n, cfl=args.cfl, t=tsim, dt_last=dt)
-
-    steps(args.warmup)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    steps(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = e0.elapsed_time(e1) / args.steps
-    value = 3.0 * dof / (ms_step * 1e-3)
-
-    mon = dg2p.monitors(mesh, P, U)
-
-    # per-kernel durations from library-recorded hipEvents on the launch stream
-    n_prof = max(1, min(args.steps, 30))
-    dg2p.timing_enable(True)
-    steps(n_prof)
-    torch.cuda.synchronize()
-    dg2p.timing_enable(False)
-    k_ms = {}
-    for name, kind in (("stage", dg2p.K_STAGE), ("ingredients", dg2p.K_INGREDIENTS),
-                       ("rate", dg2p.K_RATE), ("rate_final", dg2p.K_RATE_FINAL)):
-        k_ms[name] = dg2p.timing_read(kind)
-    # stage-kernel mean from the timed region: the step time less the other
-    # kernels' share (each measured by its own events), over 3 stage launches
-    # (events around every launch would add their own gaps to a ~15 us kernel)
-    other = sum(k_ms[k][0] * k_ms[k][1] for k in ("ingredients", "rate", "rate_final")) / n_prof
-    stage_ms = (ms_step - other) / 3.0
-    alg_bytes = (64.0 / 3.0) * dof          # per stage launch, averaged over the 3 stages
-    achieved = alg_bytes / (stage_ms * 1e-3) / 1e9
     src = source_hash()
-    traffic = recorded(args.workload, "traffic", "traffic_bytes_per_launch", src)
-    valu = recorded(args.workload, "valu", "valu_insts_per_launch", src)
 
-    # mixed-precision forms: same workload from the same initial state
+    # headline: the whole step (three stages, dt reduction, per-step monitors),
+    # the library's per-launch events recorded on its launch stream
+    ms_step, mon_rows, wall = timed_steps(mesh, P, U, args.steps, args.warmup, args.cfl,
+                                          monitored=True, events=True)
+    value = 3.0 * dof / (ms_step * 1e-3)
+    k_ms, stage_ms = stage_timing(dg2p, args.steps, ms_step)
+    rl = roofline(args.workload, dof, stage_ms, k_ms["stage"][0], src)
+    if args.workload not in HBM_RESIDENT:
+        rl["bound"] = "infinity-cache resident (fabric, not HBM)"
+    last = mon_rows[-1]
+    monitors = {"per_step": True, "steps_with_nonphys": sum(1 for r in mon_rows if r["nonphys"]),
+                "last_step": {"nonphys": last["nonphys"], "min_alpha": last["min_alpha"],
+                              "max_alpha": last["max_alpha"], "dt": last["dt"], "dev_p": last["dev_p"],
+                              "integral": last["integral"]}}
+    del U
+
     variants = {}
+    extra = {}
     if not args.no_variants:
-        # per-field error of each mixed form against the FP64 path after the
-        # workload's error horizon, both with the same fixed dt (that of the
-        # initial state), from the same initial state
-        n_err = ERROR_STEPS.get(args.workload, 100)
-        U0e = dg2p.prim_to_cons(mesh, P, dg2p.prim_tensor(
-            workloads.primitive_fields(cfg, mesh.node_coords()), cfg["dim"]))
-        dt0 = dg2p.max_dt(mesh, P, U0e, cfl=args.cfl)
-        Uref = U0e.clone()
-        dg2p.advance(mesh, P, Uref, n_err, dt_fixed=dt0)
-        Wn = torch.from_numpy(mesh.node_weights()).cuda()
-        for prec in ("fp32", "bf16"):
-            Pm = dg2p.make_params(cfg["params"], precision=prec)
-            Ue = U0e.clone()
-            dg2p.advance(mesh, Pm, Ue, n_err, dt_fixed=dt0)
-            variants[prec] = {"error_vs_fp64": field_errors(Ue, Uref, Wn, cfg["dim"], n_err)}
-            del Ue
-        del U0e, Uref
-        for prec in ("fp32", "bf16"):
-            Pm = dg2p.make_params(cfg["params"], precision=prec)
-            Um = dg2p.prim_to_cons(mesh, P, dg2p.prim_tensor(
-                workloads.primitive_fields(cfg, mesh.node_coords()), cfg["dim"]))
-            dtm = torch.empty(1, dtype=torch.float64, device="cuda")
-            dg2p.advance(mesh, Pm, Um, args.warmup, cfl=args.cfl, dt_last=dtm)
-            torch.cuda.synchronize()
-            e0.record(stream)
-            dg2p.advance(mesh, Pm, Um, args.steps, cfl=args.cfl, dt_last=dtm)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            msm = e0.elapsed_time(e1) / args.steps
-            variants[prec].update({"value": 3.0 * dof / (msm * 1e-3), "ms_per_step": msm,
-                                   "speedup_vs_fp64": ms_step / msm,
-                                   "contractions": prec, "closure_and_rk": "fp64"})
-            del Um
-
-    # adjoint form: VJP of one SSP-RK3 step on the adjoint workload (viscous +
-    # CSF droplet, 128 x 128, frozen dt), and its central-difference agreement
-    adjoint = None
+        for name in ("shock2d", "rt3d"):
+            if name == args.workload:
+                variants[name] = mixed_section(name, U0=U0, mesh=mesh, steps=args.steps, warmup=args.warmup,
+                                               cfl=args.cfl)
+            else:
+                variants[name] = mixed_section(name, steps=DEFAULT_STEPS[name], warmup=DEFAULT_STEPS[name] // 4,
+                                               cfl=args.cfl)
+            torch.cuda.empty_cache()
+    del U0
+    torch.cuda.empty_cache()
     if not args.no_variants:
-        from paper_2306_05002_amd import adjoint as adj
-        prob = adj.AdjointProblem()
-        Ua = dg2p.prim_to_cons(prob.mesh, prob.P, prob.prim0)
-        Wb = torch.randn(Ua.shape, dtype=torch.float64, device="cuda",
-                         generator=torch.Generator(device="cuda").manual_seed(0))
-        Ub = torch.empty_like(Ua)
-        sb = torch.zeros(1, dtype=torch.float64, device="cuda")
-        for _ in range(3):
-            dg2p.rk_step_vjp(prob.mesh, prob.P, Ua, prob.dt, Wb, param_bar=sb, out=Ub)
-        torch.cuda.synchronize()
-        n_adj = max(5, min(args.steps, 50))
-        e0.record(stream)
-        for _ in range(n_adj):
-            dg2p.rk_step_vjp(prob.mesh, prob.P, Ua, prob.dt, Wb, param_bar=sb, out=Ub)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms_vjp = e0.elapsed_time(e1) / n_adj
-        dof_a = prob.mesh.E * prob.mesh.nn * prob.mesh.nf
-        L0, gu, gs = prob.gradient()
-        worst = 0.0
-        h = 1e-6
-        for k in range(16):
-            du, ds = prob.fd_directions(k)
-            with torch.no_grad():
-                Lp = float(prob.loss(prob.u0 + h * du, prob.sigma0 + h * ds))
-                Lm = float(prob.loss(prob.u0 - h * du, prob.sigma0 - h * ds))
-            fd = (Lp - Lm) / (2 * h)
-            ad = float((gu * du).sum()) + gs * ds
-            worst = max(worst, abs(fd - ad) / max(abs(fd), abs(ad), 1e-300))
-        adjoint = {"workload": "adjoint2d: droplet 128x128 p=3, viscous + CSF, 400 steps, checkpoint every 20",
-                   "value": 3.0 * dof_a / (ms_vjp * 1e-3), "unit": "DOF-updates/s",
-                   "ms_per_step_vjp": ms_vjp,
-                   "step_vjp": "recompute 2 stages + 3 residual VJPs (local + gather)",
-                   "fd_directions": 16, "fd_step": h, "fd_max_rel_err": worst,
-                   "dL_dsigma": gs}
-
-    kinematic = None
-    waterair = None
-    walls = None
-    if not args.no_variants:
-        kinematic = kinematic_section()
-        waterair = waterair_section()
-        walls = walls_section()
+        extra["cache_resident_2d"] = cache_resident_section(src, args.cfl)
+        extra["adjoint"] = adjoint_section(args.steps)
+        extra["kinematic"] = kinematic_section()
+        extra["water_air_droplet"] = waterair_section()
+        extra["wall_bounded"] = walls_section()
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(cfg, args.cpu_seconds)
+        cpu = cpu_baseline(cfg, pf, args.cpu_seconds)
+    del pf
 
     out = {
         "metric": "DOF-updates/s of DG RK stage, FP64 vs mixed vs adjoint, at stated error",
@@ -487,33 +613,14 @@ def main():
             "fields": mesh.nf,
             "dof": dof,
             "precision": "fp64",
-            "step": "device dt reduction + SSP-RK3 (3 stages), dg2p_advance",
+            "step": "SSP-RK3 (3 stages) + device dt reduction + per-step monitors, dg2p_advance_monitored",
         },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "kernel": "k_stage (residual + stage combine)",
-            "kernel_mean_ms": stage_ms,
-            "kernel_event_mean_ms": k_ms["stage"][0],
-            "valu_issue": None if valu is None else {
-                "insts_per_launch": valu,
-                "issue_ms": valu / VALU_ISSUE_PER_S * 1e3,
-                "frac": valu / VALU_ISSUE_PER_S * 1e3 / stage_ms},
-            "algorithmic_bytes_per_launch": alg_bytes,
-        },
+        "roofline": rl,
         "kernels_mean_ms": {k: v[0] for k, v in k_ms.items()},
+        "monitors": monitors,
         "mixed_precision": variants,
-        "adjoint": adjoint,
-        "kinematic": kinematic,
-        "water_air_droplet": waterair,
-        "wall_bounded": walls,
+        **extra,
         "cpu_baseline": cpu,
-        "monitors": {"nonphys": mon["nonphys"], "min_alpha": mon["min_alpha"],
-                     "max_alpha": mon["max_alpha"]},
         "wall_s_timed": wall,
         "source_sha256_16": src,
     }

@@ -494,21 +494,75 @@ __device__ __forceinline__ void gradients(const KArgs& A, const double* q, const
 __device__ __forceinline__ double nan_max(double a, double b) { return (a > b || a != a) ? a : b; }
 __device__ __forceinline__ double nan_min(double a, double b) { return (a < b || a != a) ? a : b; }
 
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = nan_max(v, __shfl_xor(v, o));
-  return v;
+// ---- lane exchanges of the wave reductions, all on the vector ALU ------------
+// (a few cycles of latency each, where __shfl_xor is an LDS-routed permute).
+// gfx950's v_permlane32_swap(x, y) gives lanes 0-31 x[l + 32] and lanes 32-63
+// y[l - 32] in its second result, and leaves x[l] (lanes 0-31) / y[l]
+// (lanes 32-63) in its first; v_permlane16_swap does the same between the
+// even and odd 16-lane rows (measured).  So with x = the half a lower lane
+// keeps and y = the half an upper lane keeps, first + second is, in every
+// lane, its own half combined with the partner's same half: one step of a
+// reduce-scatter over lane mask 32 (16) without a select.
+__device__ __forceinline__ unsigned lo32(double v) { return (unsigned)(__double_as_longlong(v) & 0xffffffffull); }
+__device__ __forceinline__ unsigned hi32(double v) { return (unsigned)((unsigned long long)__double_as_longlong(v) >> 32); }
+__device__ __forceinline__ double mk64(unsigned lo, unsigned hi) {
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = nan_min(v, __shfl_xor(v, o));
-  return v;
+template <int M>
+__device__ __forceinline__ void swap_halves(double x, double y, double& a, double& b) {
+  static_assert(M == 16 || M == 32, "row-pair or half-wave swap");
+  if constexpr (M == 32) {
+    const auto l = __builtin_amdgcn_permlane32_swap(lo32(x), lo32(y), false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi32(x), hi32(y), false, false);
+    a = mk64(l[0], h[0]);
+    b = mk64(l[1], h[1]);
+  } else {
+    const auto l = __builtin_amdgcn_permlane16_swap(lo32(x), lo32(y), false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi32(x), hi32(y), false, false);
+    a = mk64(l[0], h[0]);
+    b = mk64(l[1], h[1]);
+  }
 }
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+// value of lane l ^ M for M < 16 (inside a 16-lane row).  The DPP row
+// rotation by R gives lane l the value of lane (l - R) mod 16 of its row, so
+// the rotation by 8 is xor 8, and xor 4 is the rotation by 12 (l + 4, lanes
+// with bit 2 clear) or by 4 (l - 4, bit 2 set); xor 2 and xor 1 are quad
+// permutations
+template <int M>
+__device__ __forceinline__ double xor_lane(double v) {
+  if constexpr (M == 8) {
+    return rrot<2>(v);
+  } else if constexpr (M == 4) {
+    const double back = rrot<1>(v), fwd = rrot<3>(v);
+    return (__lane_id() & 4) ? back : fwd;
+  } else if constexpr (M == 2) {
+    return dpp64<0x4E>(v);
+  } else {
+    static_assert(M == 1, "lane mask 1, 2, 4 or 8");
+    return dpp64<0xB1>(v);
+  }
 }
+// OP over the whole wave, result in every lane (0 sum, 1 max, 2 min; the
+// maximum and minimum keep NaN)
+template <int OP>
+__device__ __forceinline__ double wave_op2(double a, double b) {
+  return OP == 0 ? a + b : (OP == 1 ? nan_max(a, b) : nan_min(a, b));
+}
+template <int OP>
+__device__ __forceinline__ double wave_all(double v) {
+  double a, b;
+  swap_halves<32>(v, v, a, b);
+  v = wave_op2<OP>(a, b);
+  swap_halves<16>(v, v, a, b);
+  v = wave_op2<OP>(a, b);
+  v = wave_op2<OP>(v, xor_lane<8>(v));
+  v = wave_op2<OP>(v, xor_lane<4>(v));
+  v = wave_op2<OP>(v, xor_lane<2>(v));
+  return wave_op2<OP>(v, xor_lane<1>(v));
+}
+__device__ __forceinline__ double wave_max(double v) { return wave_all<1>(v); }
+__device__ __forceinline__ double wave_min(double v) { return wave_all<2>(v); }
+__device__ __forceinline__ double wave_sum(double v) { return wave_all<0>(v); }
 
 // Rate record of a workgroup (2 doubles: largest wave speed and largest
 // kinematic viscosity): wave max, then the workgroup's 4 waves.
@@ -609,7 +663,7 @@ __device__ __forceinline__ void node_record(const KArgs& A, const double* q, con
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
     const int a = (node >> (2 * k)) & 3;
-    W *= kCoef.w[a] * A.J[k];
+    W *= ((a == 0 || a == 3) ? GLL.w[0] : GLL.w[1]) * A.J[k];
   }
   v[R_WAVE] = valid ? w : 0.0;
   v[R_NU] = valid ? nu : 0.0;
@@ -638,37 +692,44 @@ __device__ __forceinline__ double rec_wave(int slot, double v) {
 // slots a lane carries at every step, then a plain butterfly over the
 // remaining mask bits.  Afterwards every lane l holds the wave-wide result of
 // slot l >> (6 - log2 NS).  OP: 0 = sum, 1 = max.
-template <int HALF, int OP>
-__device__ __forceinline__ void rs_step(double* v, int m, bool upper) {
+// one step over lane mask M: lanes with that bit clear keep the low half of
+// v (v[0..HALF)), the others the high half, each combined with its partner's
+// same half (lane exchanges on the vector ALU, above)
+template <int HALF, int M, int OP>
+__device__ __forceinline__ void rs_step(double* v) {
 #pragma unroll
   for (int i = 0; i < HALF; ++i) {
     const double lo = v[i], hi = v[HALF + i];
-    const double send = upper ? lo : hi;
-    const double keep = upper ? hi : lo;
-    const double got = __shfl_xor(send, m);
-    v[i] = OP == 0 ? keep + got : nan_max(keep, got);
+    if constexpr (M >= 16) {
+      double a, b;
+      swap_halves<M>(lo, hi, a, b);
+      v[i] = wave_op2<OP>(a, b);
+    } else {
+      const bool upper = (__lane_id() & M) != 0;
+      const double send = upper ? lo : hi;
+      const double keep = upper ? hi : lo;
+      v[i] = wave_op2<OP>(keep, xor_lane<M>(send));
+    }
   }
 }
-template <int OP>
-__device__ __forceinline__ double bfly(double x, int m) {
-  const double got = __shfl_xor(x, m);
-  return OP == 0 ? x + got : nan_max(x, got);
+template <int OP, int M>
+__device__ __forceinline__ double bfly(double x) {
+  return wave_op2<OP>(x, xor_lane<M>(x));
 }
 template <int NS, int OP>
 __device__ __forceinline__ double wave_reduce_scatter(double* v) {
-  const int lane = __lane_id();
   if constexpr (NS == 16) {
-    rs_step<8, OP>(v, 32, (lane & 32) != 0);
-    rs_step<4, OP>(v, 16, (lane & 16) != 0);
-    rs_step<2, OP>(v, 8, (lane & 8) != 0);
-    rs_step<1, OP>(v, 4, (lane & 4) != 0);
-    return bfly<OP>(bfly<OP>(v[0], 2), 1);
+    rs_step<8, 32, OP>(v);
+    rs_step<4, 16, OP>(v);
+    rs_step<2, 8, OP>(v);
+    rs_step<1, 4, OP>(v);
+    return bfly<OP, 1>(bfly<OP, 2>(v[0]));
   } else {
     static_assert(NS == 8, "reduce-scatter of 8 or 16 slots");
-    rs_step<4, OP>(v, 32, (lane & 32) != 0);
-    rs_step<2, OP>(v, 16, (lane & 16) != 0);
-    rs_step<1, OP>(v, 8, (lane & 8) != 0);
-    return bfly<OP>(bfly<OP>(bfly<OP>(v[0], 4), 2), 1);
+    rs_step<4, 32, OP>(v);
+    rs_step<2, 16, OP>(v);
+    rs_step<1, 8, OP>(v);
+    return bfly<OP, 1>(bfly<OP, 2>(bfly<OP, 4>(v[0])));
   }
 }
 

@@ -326,19 +326,41 @@ def test_advance_fixed_dt():
     assert max(state_errors(A.cpu(), Uo, prm, om.d)) <= 1e-12
 
 
+@pytest.mark.parametrize("ne", [(128, 128), (136, 136)])
+def test_full_grid_step_against_the_oracle(ne):
+    """One step of dg2p_advance on the full 128 x 128 droplet (1024 rate
+    records: dt reduced inside the first stage) and on 136 x 136 (1156
+    records: two-level reduction), and one dg2p_rk_step with dg2p_max_dt,
+    against the oracle's step from the same state: dt to 1e-14, every field
+    to 1e-12."""
+    cfg, om, prm, U0, mesh, P = gpu_case("drop2d", ne)
+    dg = _dg()
+    dto = oracle.max_dt(U0, om, prm)
+    Uo = oracle.rk_step(U0, dto, om, prm)
+    A = U0.cuda().contiguous()
+    last = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dg.advance(mesh, P, A, 1, cfl=0.1, dt_last=last)
+    assert abs(float(last.cpu()) - dto) <= 1e-14 * dto
+    errs = state_errors(A.cpu(), Uo, prm, om.d)
+    assert max(errs) <= 1e-12, errs
+    B = U0.cuda().contiguous()
+    dtg = dg.max_dt(mesh, P, B, cfl=0.1)
+    dg.rk_step(mesh, P, B, dtg)
+    errs = state_errors(B.cpu(), Uo, prm, om.d)
+    assert max(errs) <= 1e-12, errs
+
+
 # ---- mixed precision: error vs the FP64 oracle, stated per field -------------------
-# A-priori bound per contraction (the standard dot-product rounding bound,
-# inputs rounded once): |err| <= (n + 1) u sum_b |D_ab| |f_b - f_ref| / J with
-# n = 4 terms, sum_b |D_ab| <= 9.1, J = h / 2, u = 2^-24 (FP32) or 2^-8
-# (BF16; coefficients rounded too).  With |f - f_ref| <= 2 max|F| and
-# max|F| bounded by the parity scale S_f times h, one contraction is within
-# 5 u 9.1 * 2 * 2 = 182 u of S_f, and a residual component sums d of them:
-# 3.3e-5 for FP32 (d = 3) and O(1) for BF16 -- the bars below.
+# The per-node a-priori rounding bound of the contractions is tested where it
+# applies exactly (tests/test_gpu_mixed.py).  On the full workloads the
+# interface flux, the normal and the curvature are themselves contracted
+# fields, so errors compound; the bars below are the largest measured normwise
+# field errors of one residual (FP32 1.3e-7, BF16 1.3e-2) with a margin of 8x.
 MIXED = [("drop2d", (9, 7)), ("shock2d", (12, 6)), ("adjoint2d", (8, 7)), ("rt3d", (3, 4, 3)),
          ("drop1d", (19,))]
 
 
-@pytest.mark.parametrize("prec,bar", [("fp32", 3.3e-5), ("bf16", 2.2)])
+@pytest.mark.parametrize("prec,bar", [("fp32", 1e-6), ("bf16", 0.1)])
 @pytest.mark.parametrize("name,ne", MIXED)
 def test_mixed_precision_rhs_error(name, ne, prec, bar):
     cfg, om, prm, U0, mesh, P = gpu_case(name, ne)
