@@ -40,7 +40,7 @@ __device__ __forceinline__ void kin_flux(const KArgs& A, double phi, const doubl
   double g2 = 0.0;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) g2 = fma(gpsi[k], gpsi[k], g2);
-  const double inv = 1.0 / sqrt(g2 + A.delta * A.delta);
+  const double inv = rsqrt_nr(g2 + A.delta * A.delta);
   const double pp = phi * (1.0 - phi);
 #pragma unroll
   for (int k = 0; k < DIM; ++k) a[k] = A.Gamma * (A.eps * gphi[k] - pp * (gpsi[k] * inv));
