@@ -111,6 +111,7 @@ KArgs make_args(const dg2p_mesh_s* m, const dg2p_params* p) {
     A.N[k] = k < m->dim ? m->N[k] : 1;
     for (int s = 0; s < 2; ++s) {
       A.bc[k][s] = k < m->dim ? m->desc.bc[k][s] : DG2P_BC_PERIODIC;
+      A.bc_bits |= (unsigned)A.bc[k][s] << (3 * (2 * k + s));
       for (int f = 0; f < 8; ++f) A.bcs[k][s][f] = m->desc.bc_state[k][s][f];
     }
     const double J = k < m->dim ? m->J[k] : 1.0;

@@ -152,6 +152,10 @@ struct KArgs {
   long long xcd_chunk;  // logical workgroups per XCD slab
   int N[3];
   int bc[3][2];
+  // the same boundary kinds, 3 bits per side at bit 3 (2k + side): read with
+  // a per-lane side as a shift of a kernel argument (bc_kind), not as an
+  // indexed load that the compiler would wait for at once
+  unsigned bc_bits;
   double bcs[3][2][8];
   double Jinv[3];
   double lift[3];       // 1 / (w_0 J_k): face-to-node lift under GLL collocation
@@ -177,6 +181,11 @@ struct KArgs {
   double cfl, hmin;
   long long nrate;  // number of rate records
 };
+
+// Boundary kind of side `side` of axis k (both may vary between lanes).
+__device__ __forceinline__ int bc_kind(const KArgs& A, int k, int side) {
+  return (int)((A.bc_bits >> (3 * (2 * k + side))) & 7u);
+}
 
 struct StageIO {
   const double* Us;   // stage input state
@@ -916,6 +925,28 @@ __device__ __forceinline__ double pick(const double* v, int k) {
   }
 }
 
+// The same for a kernel-argument array (uniform values) with an axis that
+// may vary between lanes: both candidates are pinned in scalar registers
+// first, so that the selection stays a per-lane select of scalars (the
+// compiler would otherwise turn it into a per-lane load from the argument
+// segment, waited for at once).
+template <int DIM>
+__device__ __forceinline__ double pick_arg(const double* v, int k) {
+  if constexpr (DIM == 1) {
+    return v[0];
+  } else {
+    double a = v[0], b = v[1];
+    asm volatile("" : "+s"(a), "+s"(b));
+    if constexpr (DIM == 2) {
+      return k ? b : a;
+    } else {
+      double c = v[2];
+      asm volatile("" : "+s"(c));
+      return k == 0 ? a : (k == 1 ? b : c);
+    }
+  }
+}
+
 // Convective flux of conservative equation qi along axis kd (velocity
 // component uk = u_kd).
 template <int DIM>
@@ -971,7 +1002,7 @@ __device__ __forceinline__ void face_flux(const KArgs& A, int kd, int side, bool
       for (int j = 0; j < DIM; ++j) tek[j] = tn[j];
     }
   } else {
-    const int kind = A.bc[kd][side];
+    const int kind = bc_kind(A, kd, side);
 #pragma unroll
     for (int f = 0; f < NF; ++f) qe[f] = q[f];
     aek = a_k;
@@ -1039,9 +1070,9 @@ __device__ __forceinline__ void face_flux(const KArgs& A, int kd, int side, bool
   const double amI = sm * a_k, amE = sm * aek;
   const double alI = q[3 + DIM], alE = qe[3 + DIM];
   const double jump = alI - alE;
-  const double penk = pick<DIM>(A.pen, kd);
+  const double penk = pick_arg<DIM>(A.pen, kd);
   const double ahat = 0.5 * (amI + amE) - penk * A.GammaEps * jump;
-  const double Lf = pick<DIM>(A.lift, kd);
+  const double Lf = pick_arg<DIM>(A.lift, kd);
   double etav = 0.0;
   if constexpr (VISC) {
     const double mue = A.mu1 * alE + A.mu2 * (1.0 - alE);
@@ -1088,6 +1119,24 @@ __device__ __forceinline__ void face_flux(const KArgs& A, int kd, int side, bool
   Rc[4 + DIM] = Lf * (0.5 * (lam - umI) * (qe[4 + DIM] - q[4 + DIM]));
 }
 
+// One of four compile-time values by a lane's node position a (selects, no
+// table load: a load here would be waited for at once, and the in-order
+// memory counters would make that wait drain every load in flight).
+__device__ __forceinline__ double pick4(int a, double v0, double v1, double v2, double v3) {
+  double v = v0;
+  v = a == 1 ? v1 : v;
+  v = a == 2 ? v2 : v;
+  return a == 3 ? v3 : v;
+}
+// SIPG spread weights D[end][a] / w_a of the line's low (end 0) and high
+// (end 3) face
+__device__ __forceinline__ double spread_lo(int a) {
+  return pick4(a, GLL.D[0][0] / GLL.w[0], GLL.D[0][1] / GLL.w[1], GLL.D[0][2] / GLL.w[2], GLL.D[0][3] / GLL.w[3]);
+}
+__device__ __forceinline__ double spread_hi(int a) {
+  return pick4(a, GLL.D[3][0] / GLL.w[0], GLL.D[3][1] / GLL.w[1], GLL.D[3][2] / GLL.w[2], GLL.D[3][3] / GLL.w[3]);
+}
+
 // SIPG symmetric term: the values symv of the face nodes at the two ends of
 // each line along K, weighted with D[end][a] / (2 w_a J_K^2) (end = 0 for the
 // low face, 3 for the high face), added to every node a of the line.
@@ -1099,7 +1148,7 @@ __device__ __forceinline__ void spread_sym(const KArgs& A, int akk, const double
     // S[a][b] = D[b][a] / (2 w_a J_z^2) for the line ends b in {0, 3}
     // (akk is a_z; the lane's operator entry is S[a_x][a_z])
     const int ax = __lane_id() & 3;
-    const double m = kCoef.szt[ax][akk] * A.hJ2inv[2];
+    const double m = (akk == 0 ? spread_lo(ax) : (akk == 3 ? spread_hi(ax) : 0.0)) * A.hJ2inv[2];
 #pragma unroll
     for (int i = 0; i <= NC; ++i) {
       const int f = (i < NC) ? i : 3 + DIM;
@@ -1107,8 +1156,8 @@ __device__ __forceinline__ void spread_sym(const KArgs& A, int akk, const double
     }
     return;
   }
-  const double wlo = kCoef.sp[0][akk] * A.hJ2inv[K];
-  const double whi = kCoef.sp[1][akk] * A.hJ2inv[K];
+  const double wlo = spread_lo(akk) * A.hJ2inv[K];
+  const double whi = spread_hi(akk) * A.hJ2inv[K];
 #pragma unroll
   for (int i = 0; i <= NC; ++i) {
     const double lo = line_end<K>(symv[i], akk, false);
@@ -1148,6 +1197,12 @@ __global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs
   double q[NF];
 #pragma unroll
   for (int f = 0; f < NF; ++f) q[f] = Us[(f * A.E + e) * NN + node];
+  // the step's dt (written before this launch), loaded now rather than at
+  // the combine, where its wait would stall the wave
+  double dt_in = 0.0;
+  if constexpr (MODE != 0) {
+    if (!(MODE == 1 && io.dt_out)) dt_in = *io.dt;
+  }
   // first stage of a small grid: the rate records of the time step
   __shared__ double dt_lds[2][BLOCK / 64];
   if constexpr (MODE == 1) {
@@ -1166,7 +1221,7 @@ __global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs
     long long c = ec[k] + (side ? 1 : -1);
     bool bnd = false;
     if (c < 0 || c >= A.N[k]) {
-      if (BCK == 0 || A.bc[k][side] == DG2P_BC_PERIODIC)
+      if (BCK == 0 || bc_kind(A, k, side) == DG2P_BC_PERIODIC)
         c = (c < 0) ? A.N[k] - 1 : 0;
       else
         bnd = true;
@@ -1195,7 +1250,7 @@ __global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs
     } else {
       long long c = ec[1] + (jside ? 1 : -1);
       if (c < 0 || c >= A.N[1]) {
-        if (BCK == 0 || (jside ? A.bc[1][1] : A.bc[1][0]) == DG2P_BC_PERIODIC)
+        if (BCK == 0 || bc_kind(A, 1, jside) == DG2P_BC_PERIODIC)
           c = (c < 0) ? A.N[1] - 1 : 0;
         else
           jbnd = true;
@@ -1210,6 +1265,67 @@ __global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs
   closure<DIM>(A, q, pr);
   Grad<DIM, VISC> g;
   gradients<DIM, VISC, PR>(A, q, pr, L, g);
+  // Hexahedra: the z-face neighbour traces and, in the later stages, U^n of
+  // the stage combination go straight from HBM into LDS with gfx950's
+  // global-to-LDS transfers (16 bytes per lane, lane l landing at byte 16 l of
+  // the destination), issued here, once the closure and the gradients have
+  // consumed the element's own loads (after a transfer the compiler's waits
+  // drain every outstanding load), so that they are in flight during the
+  // volume terms and hold no registers.  The kernel waits for them itself
+  // (vmcnt 0) before the z-face pass reads LDS.
+  //   z traces (3 transfers per wave, 1 KB each): the 16 nodes of the layer of
+  //   the neighbour below (its top layer) and above (its bottom layer) are
+  //   contiguous, so lane l = 16 c + 8 s + p fetches doubles 2p, 2p + 1 of
+  //   component c of side s (0 below, 1 above): state fields 0-3, 4-7, and the
+  //   face ingredients (a.e_z, tau.e_z) the neighbour published for that face.
+  //   Slice zt[w][t][32 c + 16 s + face node].
+  //   U^n (4 transfers): lanes 0-31 fetch field 2i, lanes 32-63 field 2i + 1:
+  //   slice un[w][f][node].
+  constexpr bool Z_LDS = DIM == 3;
+  constexpr bool UN_LDS = DIM == 3 && MODE == 2;
+  __shared__ __attribute__((aligned(16))) double zt_lds[Z_LDS ? BLOCK / 64 : 1][Z_LDS ? 3 : 1][Z_LDS ? 128 : 1];
+  __shared__ __attribute__((aligned(16))) double un_lds[UN_LDS ? BLOCK / 64 : 1][UN_LDS ? NF : 1][UN_LDS ? NN : 1];
+  if constexpr (Z_LDS) {
+    constexpr int C = VISC ? 1 + DIM : 1;
+    const int w = threadIdx.x >> 6;
+    const int sd = (lane >> 3) & 1, part = lane & 7, cc = lane >> 4;
+    // z-neighbour on side sd (uniform in the wave: one element per wave); a
+    // boundary side fetches the element itself (in bounds, unused: ghost)
+    long long en = e;
+    {
+      long long c = ec[2] + (sd ? 1 : -1);
+      bool bnd = false;
+      if (c < 0 || c >= A.N[2]) {
+        if (BCK == 0 || bc_kind(A, 2, sd) == DG2P_BC_PERIODIC)
+          c = (c < 0) ? A.N[2] - 1 : 0;
+        else
+          bnd = true;
+      }
+      if (!bnd) en = e + (c - ec[2]) * ((long long)A.N[0] * A.N[1]);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const double* src = Us + ((long long)(4 * t + cc) * A.E + en) * NN + (sd ? 0 : 48) + 2 * part;
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src),
+                                       (__attribute__((address_space(3))) void*)&zt_lds[w][t][0], 16, 0, 0);
+    }
+    {
+      const int comp = cc < C ? cc : C - 1;
+      const double* src = io.Gin + ((long long)((5 - sd) * C + comp) * A.E + en) * (NN / 4) + 2 * part;
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src),
+                                       (__attribute__((address_space(3))) void*)&zt_lds[w][2][0], 16, 0, 0);
+    }
+  }
+  if constexpr (UN_LDS) {
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NF / 2; ++i) {
+      const int f = 2 * i + (lane >> 5);
+      const double* src = io.Un + (f * A.E + e) * NN + 2 * (lane & 31);
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src),
+                                       (__attribute__((address_space(3))) void*)&un_lds[w][2 * i][0], 16, 0, 0);
+    }
+  }
 
   double R[NF];
   // volume terms, strong form: R_q = sum_k (1/J_k) D_k (-F_q + s_q a + V_q)_k
@@ -1353,6 +1469,8 @@ __global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs
     }
     spread_sym<(DIM > 1 ? 1 : 0), DIM>(A, ak[1], symv, R);
   }
+  // the transfers into LDS issued at entry have landed (uniform point)
+  if constexpr (Z_LDS) __builtin_amdgcn_s_waitcnt(0x0f70);
   {
     // 1D: its faces; 3D: the z-faces (lanes with a_z in {0, 3})
     constexpr int K0 = DIM >= 2 ? 2 : 0;
@@ -1376,8 +1494,18 @@ __global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs
           nhk = g.nh[k];
         }
         double qk[NF], ank, tk[DIM];
-        face_load<DIM, VISC>(A, Us, Gin, k, akk == 3, enb[k], node + (3 - 2 * akk) * S, face_index(node, k), qk,
-                             ank, tk);
+        if constexpr (Z_LDS) {
+          const int w = threadIdx.x >> 6;
+          const int slot = 16 * (akk == 3) + (node & 15);
+#pragma unroll
+          for (int f = 0; f < NF; ++f) qk[f] = zt_lds[w][f >> 2][32 * (f & 3) + slot];
+          ank = zt_lds[w][2][slot];
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) tk[j] = VISC ? zt_lds[w][2][32 * (1 + j) + slot] : 0.0;
+        } else {
+          face_load<DIM, VISC>(A, Us, Gin, k, akk == 3, enb[k], node + (3 - 2 * akk) * S, face_index(node, k), qk,
+                               ank, tk);
+        }
         face_flux<DIM, VISC, BCK>(A, k, akk == 3, bndk[k], qk, ank, tk, q, pr, g.a[k], g.mu, Sk, gAk, nhk, Rc, symv);
 #pragma unroll
         for (int f = 0; f < NF; ++f) R[f] += Rc[f];
@@ -1407,11 +1535,17 @@ __global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs
       for (int f = 0; f < NF; ++f) io.Out[f * fs + o] = R[f];
     }
   } else {
-    const double dt = (MODE == 1 && io.dt_out) ? dt_fused : *io.dt;
+    const double dt = (MODE == 1 && io.dt_out) ? dt_fused : dt_in;
     double uo[NF];
     if constexpr (MODE == 1) {
 #pragma unroll
       for (int f = 0; f < NF; ++f) uo[f] = q[f] + dt * R[f];
+    } else if constexpr (UN_LDS) {
+      // U^n from the wave's LDS slice (its transfer was waited for before
+      // the z-face pass)
+      const int w = threadIdx.x >> 6;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) uo[f] = A.rk_a * un_lds[w][f][node] + A.rk_b * (q[f] + dt * R[f]);
     } else {
 #pragma unroll
       for (int f = 0; f < NF; ++f) uo[f] = A.rk_a * io.Un[f * fs + o] + A.rk_b * (q[f] + dt * R[f]);
