@@ -1183,7 +1183,11 @@ __global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs
   const long long blk = logical_block(A);
   if (blk < 0) return;
   const int lane = threadIdx.x & 63;
-  const long long e0 = (blk * (BLOCK / 64) + (threadIdx.x >> 6)) * EPW + lane / NN;
+  // the wave's index in the workgroup, uniform by construction: read through
+  // readfirstlane so that for hexahedra (one element per wave) the element,
+  // its grid coordinates, neighbours and boundary tests are scalar values
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const long long e0 = (blk * (BLOCK / 64) + wv) * EPW + lane / NN;
   const bool valid = e0 < A.E;
   const long long e = valid ? e0 : A.E - 1;
   const int node = lane % NN;
@@ -1260,6 +1264,9 @@ __global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs
     const int nodee = xjob ? node + (3 - 2 * ak[0]) : onode + (jside ? -12 : 12);
     const int fn = DIM == 2 ? (xjob ? (node >> 2) : ak[1]) : (xjob ? face_index(node, 0) : face_index(onode, 1));
     face_load<DIM, VISC>(A, Us, io.Gin, xjob ? 0 : 1, jside, en, nodee, fn, qn, an, tn);
+    // issue these loads before the closure waits for the element's own state
+    // (the scheduler would otherwise place them behind it)
+    if constexpr (DIM == 3) __builtin_amdgcn_sched_barrier(0);
   }
   Prim pr;
   closure<DIM>(A, q, pr);
