@@ -325,6 +325,13 @@ int dg2p_kin_rk4(dg2p_mesh m, const dg2p_kin_params* kp /*host*/, double* Phi /*
 int dg2p_kin_reinit(dg2p_mesh m, const dg2p_kin_params* kp /*host*/, double* Phi /*device, in/out*/, int n_iter,
                     double nu, double dtau, void* work /*device*/, void* stream);
 
+/* Parameters of dg2p_kin_reinit used for the paper's runs (host outputs; the
+ * paper states neither): *nu = h_min / (p+1), one nodal spacing (the
+ * viscosity "proportional to the grid size"), and the pseudo step
+ * *dtau = cfl h_min / (1 + (p+1)^2 d nu / h_min), the time-step rule of
+ * unit-speed transport with that viscosity. */
+int dg2p_kin_reinit_params(dg2p_mesh m, double cfl, double* nu /*host*/, double* dtau /*host*/);
+
 /* Time step *dt (device scalar) = cfl h_min / (max_nodes sum_k |u0_k| +
  * (p+1)^2 d Gamma eps / h_min): the rule of dg2p_max_dt without the sound
  * speed.  work: DG2P_OP_KIN_AUX bytes. */

@@ -16,6 +16,7 @@
 #include "dg2p_device.hpp"
 #include "dg2p_adjoint.hpp"
 #include "dg2p_kinematic.hpp"
+#include "dg2p_kinematic_p1.hpp"
 #include "dg2p_launch.hpp"
 
 using namespace dg2p;
@@ -52,26 +53,33 @@ int hip_check(hipError_t e, const char* what) {
   return fail(DG2P_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-// GLL nodes and weights of degree 3 in closed form, and the Lagrange
+// GLL nodes and weights of degree 3 (or 1) in closed form, and the Lagrange
 // derivative matrix D[a][b] = l_b'(xi_a) from the product rule.
-void gll3(double* x, double* w, double (*D)[4]) {
-  const double s = 1.0 / std::sqrt(5.0);
-  x[0] = -1.0;
-  x[1] = -s;
-  x[2] = s;
-  x[3] = 1.0;
-  w[0] = w[3] = 1.0 / 6.0;
-  w[1] = w[2] = 5.0 / 6.0;
-  for (int a = 0; a < 4; ++a) {
-    for (int b = 0; b < 4; ++b) {
+void gll(int p, double* x, double* w, double (*D)[4]) {
+  const int n = p + 1;
+  if (p == 1) {
+    x[0] = -1.0;
+    x[1] = 1.0;
+    w[0] = w[1] = 1.0;
+  } else {
+    const double s = 1.0 / std::sqrt(5.0);
+    x[0] = -1.0;
+    x[1] = -s;
+    x[2] = s;
+    x[3] = 1.0;
+    w[0] = w[3] = 1.0 / 6.0;
+    w[1] = w[2] = 5.0 / 6.0;
+  }
+  for (int a = 0; a < n; ++a) {
+    for (int b = 0; b < n; ++b) {
       if (a == b) {
         double t = 0.0;
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < n; ++m)
           if (m != a) t += 1.0 / (x[a] - x[m]);
         D[a][b] = t;
       } else {
         double num = 1.0, den = 1.0;
-        for (int m = 0; m < 4; ++m) {
+        for (int m = 0; m < n; ++m) {
           if (m != b) den *= (x[b] - x[m]);
           if (m != a && m != b) num *= (x[a] - x[m]);
         }
@@ -83,6 +91,8 @@ void gll3(double* x, double* w, double (*D)[4]) {
 
 int check_params(const dg2p_mesh_s* m, const dg2p_params* p) {
   if (!p) return fail(DG2P_EINVAL, "params is NULL");
+  if (m && m->desc.order != 3)
+    return fail(DG2P_EUNSUPPORTED, "the two-phase model is implemented for p = 3 (p = 1: kinematic mode only)");
   for (int l = 0; l < 2; ++l) {
     if (!(p->gamma[l] > 1.0)) return fail(DG2P_EINVAL, "gamma must be > 1");
     if (!std::isfinite(p->pinf[l]) || !std::isfinite(p->rho0[l]))
@@ -118,7 +128,7 @@ KArgs make_args(const dg2p_mesh_s* m, const dg2p_params* p) {
     const double h = k < m->dim ? m->h[k] : 1.0;
     A.Jinv[k] = 1.0 / J;
     A.lift[k] = 1.0 / (m->w[0] * J);
-    A.pen[k] = p->c_ip * 16.0 / h;
+    A.pen[k] = p->c_ip * (double)((m->desc.order + 1) * (m->desc.order + 1)) / h;
     A.J[k] = J;
     A.hJ2inv[k] = 1.0 / (2.0 * J * J);
   }
@@ -376,7 +386,8 @@ void finalize_rate(const dg2p_mesh_s* m, const KArgs& A, const Work& w, long lon
     src = w.rec2;
     n = nb;
   }
-  hipLaunchKernelGGL(k_finalize_rate, dim3(1), dim3(FIN_THREADS), 0, s, src, n, A.GammaEps, m->dim, min_h(m), cfl,
+  const double pdim = (double)((m->desc.order + 1) * (m->desc.order + 1) * m->dim);
+  hipLaunchKernelGGL(k_finalize_rate, dim3(1), dim3(FIN_THREADS), 0, s, src, n, A.GammaEps, pdim, min_h(m), cfl,
                      dt_fixed, dt, t);
 }
 
@@ -466,6 +477,7 @@ void kin_ingr_d(const KArgs& A, const double* P, double* G, hipStream_t s) {
   hipLaunchKernelGGL(k_kin_ingredients<DIM>, elem_grid(A), dim3(BLOCK), 0, s, A, P, G);
 }
 void kin_ingr(const dg2p_mesh_s* m, const KArgs& A, const double* P, double* G, hipStream_t s) {
+  if (m->desc.order == 1) return;  // the p = 1 kernels differentiate the neighbours themselves
   if (m->dim == 1) kin_ingr_d<1>(A, P, G, s);
   else if (m->dim == 2) kin_ingr_d<2>(A, P, G, s);
   else kin_ingr_d<3>(A, P, G, s);
@@ -478,7 +490,21 @@ void kin_stage_d(int mode, const KArgs& A, const KinIO& io, hipStream_t s) {
   else if (mode == 1) hipLaunchKernelGGL((k_kin_stage<DIM, 1>), g, b, 0, s, A, io);
   else hipLaunchKernelGGL((k_kin_stage<DIM, 2>), g, b, 0, s, A, io);
 }
+template <int DIM>
+void kin1_stage_d(int mode, const KArgs& A, const KinIO& io, hipStream_t s) {
+  TimedLaunch t(DG2P_K_KIN_STAGE, s);
+  const dim3 g((unsigned)((A.E + BLOCK - 1) / BLOCK)), b(BLOCK);
+  if (mode == 0) hipLaunchKernelGGL((k_kin1_stage<DIM, 0>), g, b, 0, s, A, io);
+  else if (mode == 1) hipLaunchKernelGGL((k_kin1_stage<DIM, 1>), g, b, 0, s, A, io);
+  else hipLaunchKernelGGL((k_kin1_stage<DIM, 2>), g, b, 0, s, A, io);
+}
 void kin_stage(const dg2p_mesh_s* m, int mode, const KArgs& A, const KinIO& io, hipStream_t s) {
+  if (m->desc.order == 1) {
+    if (m->dim == 1) kin1_stage_d<1>(mode, A, io, s);
+    else if (m->dim == 2) kin1_stage_d<2>(mode, A, io, s);
+    else kin1_stage_d<3>(mode, A, io, s);
+    return;
+  }
   if (m->dim == 1) kin_stage_d<1>(mode, A, io, s);
   else if (m->dim == 2) kin_stage_d<2>(mode, A, io, s);
   else kin_stage_d<3>(mode, A, io, s);
@@ -567,7 +593,8 @@ int dg2p_create_mesh(const dg2p_mesh_desc* desc, dg2p_mesh* out) {
   if (!desc || !out) return fail(DG2P_EINVAL, "desc and out must be non-NULL");
   *out = nullptr;
   if (desc->dim < 1 || desc->dim > 3) return fail(DG2P_EINVAL, "dim must be 1, 2 or 3");
-  if (desc->order != 3) return fail(DG2P_EUNSUPPORTED, "only polynomial order 3 is implemented");
+  if (desc->order != 3 && desc->order != 1)
+    return fail(DG2P_EUNSUPPORTED, "polynomial order 3 (and 1 for the kinematic mode) is implemented");
   long long E = 1;
   for (int k = 0; k < desc->dim; ++k) {
     if (desc->n_elem[k] < 1) return fail(DG2P_EINVAL, "n_elem must be >= 1");
@@ -583,7 +610,9 @@ int dg2p_create_mesh(const dg2p_mesh_desc* desc, dg2p_mesh* out) {
       return fail(DG2P_EINVAL, "periodic must be set on both sides of an axis");
     E *= desc->n_elem[k];
   }
-  const long long nn = 1LL << (2 * desc->dim);
+  const int np1 = desc->order + 1;
+  long long nn = 1;
+  for (int k = 0; k < desc->dim; ++k) nn *= np1;
   if (E > (1LL << 40) / nn) return fail(DG2P_EINVAL, "mesh too large");
   // element indices are formed in 32 bits inside the kernels
   if (E >= (1LL << 31)) return fail(DG2P_EINVAL, "mesh has 2^31 or more elements");
@@ -594,13 +623,13 @@ int dg2p_create_mesh(const dg2p_mesh_desc* desc, dg2p_mesh* out) {
   m->E = E;
   m->nn = (int)nn;
   m->nf = desc->dim + 5;
-  m->nfn = (int)(nn / 4);
+  m->nfn = (int)(nn / np1);
   for (int k = 0; k < 3; ++k) {
     m->N[k] = k < desc->dim ? desc->n_elem[k] : 1;
     m->h[k] = k < desc->dim ? (desc->hi[k] - desc->lo[k]) / desc->n_elem[k] : 1.0;
     m->J[k] = 0.5 * m->h[k];
   }
-  gll3(m->xi, m->w, m->D);
+  gll(desc->order, m->xi, m->w, m->D);
   *out = m;
   return DG2P_OK;
 }
@@ -627,7 +656,9 @@ int dg2p_node_coords(dg2p_mesh m, double* xyz) {
     for (long long e = 0; e < E; ++e) {
       const long long ek = (e / stride) % m->N[k];
       for (int j = 0; j < m->nn; ++j) {
-        const int a = (j >> (2 * k)) & 3;
+        int a = j;
+        for (int kk = 0; kk < k; ++kk) a /= (m->desc.order + 1);
+        a %= (m->desc.order + 1);
         xyz[((long long)k * E + e) * m->nn + j] =
             m->desc.lo[k] + m->h[k] * (double)ek + m->J[k] * (m->xi[a] + 1.0);
       }
@@ -695,7 +726,11 @@ int dg2p_node_weights(dg2p_mesh m, double* W) {
   if (!m || !W) return fail(DG2P_EINVAL, "mesh and W must be non-NULL");
   for (int j = 0; j < m->nn; ++j) {
     double w = 1.0;
-    for (int k = 0; k < m->dim; ++k) w *= m->w[(j >> (2 * k)) & 3] * m->J[k];
+    int r = j;
+    for (int k = 0; k < m->dim; ++k) {
+      w *= m->w[r % (m->desc.order + 1)] * m->J[k];
+      r /= (m->desc.order + 1);
+    }
     W[j] = w;
   }
   return DG2P_OK;
@@ -1049,6 +1084,7 @@ int dg2p_kin_reinit(dg2p_mesh m, const dg2p_kin_params* kp, double* Phi, int n_i
   if (!(nu > 0.0) || !std::isfinite(nu) || !std::isfinite(dtau)) return fail(DG2P_EINVAL, "nu > 0, finite dtau");
   int st = check_kin(m, kp);
   if (st) return st;
+  if (m->desc.order != 3) return fail(DG2P_EUNSUPPORTED, "the re-initialisation is implemented for p = 3");
   st = check_ws(work, kin_work_bytes(m, DG2P_OP_KIN_RK4));
   if (st) return st;
   // the SIPG coefficient of the diffusive flux is nu: Gamma eps := 1 * nu
@@ -1092,6 +1128,17 @@ int dg2p_kin_reinit(dg2p_mesh m, const dg2p_kin_params* kp, double* Phi, int n_i
   return hip_check(hipGetLastError(), "kin_reinit launch");
 }
 
+int dg2p_kin_reinit_params(dg2p_mesh m, double cfl, double* nu, double* dtau) {
+  g_last_error.clear();
+  if (!m || !nu || !dtau) return fail(DG2P_EINVAL, "mesh, nu and dtau must be non-NULL");
+  if (!(cfl > 0.0)) return fail(DG2P_EINVAL, "cfl must be > 0");
+  const double hmin = min_h(m);
+  const int p = m->desc.order;
+  *nu = hmin / (p + 1);
+  *dtau = cfl * hmin / (1.0 + (double)((p + 1) * (p + 1) * m->dim) * (*nu) / hmin);
+  return DG2P_OK;
+}
+
 int dg2p_kin_max_dt(dg2p_mesh m, const dg2p_kin_params* kp, const double* u0, double cfl, double* dt, void* work,
                     void* stream) {
   g_last_error.clear();
@@ -1106,13 +1153,25 @@ int dg2p_kin_max_dt(dg2p_mesh m, const dg2p_kin_params* kp, const double* u0, do
   Work w;
   w.rec = static_cast<double*>(work);
   w.rec2 = w.rec + RATE * elem_blocks(m);
+  long long nrec = elem_blocks(m);
   {
     TimedLaunch t(DG2P_K_RATE, s);
-    if (m->dim == 1) hipLaunchKernelGGL(k_kin_rate<1>, elem_grid(A), dim3(BLOCK), 0, s, A, u0, w.rec);
-    else if (m->dim == 2) hipLaunchKernelGGL(k_kin_rate<2>, elem_grid(A), dim3(BLOCK), 0, s, A, u0, w.rec);
-    else hipLaunchKernelGGL(k_kin_rate<3>, elem_grid(A), dim3(BLOCK), 0, s, A, u0, w.rec);
+    if (m->desc.order == 1) {
+      const long long n = m->E * m->nn;
+      nrec = (n + BLOCK - 1) / BLOCK;
+      const dim3 g((unsigned)nrec);
+      if (m->dim == 1) hipLaunchKernelGGL(k_kin1_rate<1>, g, dim3(BLOCK), 0, s, n, u0, w.rec);
+      else if (m->dim == 2) hipLaunchKernelGGL(k_kin1_rate<2>, g, dim3(BLOCK), 0, s, n, u0, w.rec);
+      else hipLaunchKernelGGL(k_kin1_rate<3>, g, dim3(BLOCK), 0, s, n, u0, w.rec);
+    } else if (m->dim == 1) {
+      hipLaunchKernelGGL(k_kin_rate<1>, elem_grid(A), dim3(BLOCK), 0, s, A, u0, w.rec);
+    } else if (m->dim == 2) {
+      hipLaunchKernelGGL(k_kin_rate<2>, elem_grid(A), dim3(BLOCK), 0, s, A, u0, w.rec);
+    } else {
+      hipLaunchKernelGGL(k_kin_rate<3>, elem_grid(A), dim3(BLOCK), 0, s, A, u0, w.rec);
+    }
   }
-  finalize_rate(m, A, w, elem_blocks(m), cfl, nullptr, dt, nullptr, s);
+  finalize_rate(m, A, w, nrec, cfl, nullptr, dt, nullptr, s);
   return hip_check(hipGetLastError(), "kin_max_dt launch");
 }
 
@@ -1126,9 +1185,18 @@ int dg2p_kin_errors(dg2p_mesh m, const double* phi, const double* phi0, double* 
   hipStream_t s = (hipStream_t)stream;
   double* rec = static_cast<double*>(work);
   const long long nb = kin_err_blocks(m);
-  if (m->dim == 1) hipLaunchKernelGGL(k_kin_errors<1>, dim3((unsigned)nb), dim3(BLOCK), 0, s, A, phi, phi0, rec);
-  else if (m->dim == 2) hipLaunchKernelGGL(k_kin_errors<2>, dim3((unsigned)nb), dim3(BLOCK), 0, s, A, phi, phi0, rec);
-  else hipLaunchKernelGGL(k_kin_errors<3>, dim3((unsigned)nb), dim3(BLOCK), 0, s, A, phi, phi0, rec);
+  const long long n = m->E * m->nn;
+  if (m->desc.order == 1) {
+    if (m->dim == 1) hipLaunchKernelGGL(k_kin1_errors<1>, dim3((unsigned)nb), dim3(BLOCK), 0, s, A, n, phi, phi0, rec);
+    else if (m->dim == 2) hipLaunchKernelGGL(k_kin1_errors<2>, dim3((unsigned)nb), dim3(BLOCK), 0, s, A, n, phi, phi0, rec);
+    else hipLaunchKernelGGL(k_kin1_errors<3>, dim3((unsigned)nb), dim3(BLOCK), 0, s, A, n, phi, phi0, rec);
+  } else if (m->dim == 1) {
+    hipLaunchKernelGGL(k_kin_errors<1>, dim3((unsigned)nb), dim3(BLOCK), 0, s, A, phi, phi0, rec);
+  } else if (m->dim == 2) {
+    hipLaunchKernelGGL(k_kin_errors<2>, dim3((unsigned)nb), dim3(BLOCK), 0, s, A, phi, phi0, rec);
+  } else {
+    hipLaunchKernelGGL(k_kin_errors<3>, dim3((unsigned)nb), dim3(BLOCK), 0, s, A, phi, phi0, rec);
+  }
   hipLaunchKernelGGL(k_kin_sum, dim3(1), dim3(FIN_THREADS), 0, s, rec, nb, 3, out);
   return hip_check(hipGetLastError(), "kin_errors launch");
 }

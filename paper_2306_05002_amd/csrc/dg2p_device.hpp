@@ -637,10 +637,11 @@ __device__ __forceinline__ void block_rate_record(double w, double nu, double* r
 }
 
 // Time-step rule from the reduced maxima: rate = (max wave + (p+1)^2 d
-// nu_max / h_min) / h_min with nu_max = max(Gamma eps, max mu/rho).
-__device__ __forceinline__ double rate_of(double wmax, double numax, double GammaEps, int dim, double hmin) {
+// nu_max / h_min) / h_min with nu_max = max(Gamma eps, max mu/rho);
+// pdim = (p+1)^2 d.
+__device__ __forceinline__ double rate_of(double wmax, double numax, double GammaEps, double pdim, double hmin) {
   const double nu = nan_max(GammaEps, numax);
-  return (wmax + 16.0 * dim * nu / hmin) / hmin;
+  return (wmax + pdim * nu / hmin) / hmin;
 }
 
 // Fused time step of a small grid: every workgroup reduces all rate records
@@ -689,7 +690,7 @@ __device__ __forceinline__ double fused_dt_finish(const KArgs& A, double (*sh)[B
     w = nan_max(w, sh[0][i]);
     nu = nan_max(nu, sh[1][i]);
   }
-  return A.cfl / rate_of(w, nu, A.GammaEps, dim, A.hmin);
+  return A.cfl / rate_of(w, nu, A.GammaEps, 16.0 * dim, A.hmin);
 }
 
 // Per-node record contributions of a state (time-step rate and monitors).
@@ -1543,19 +1544,21 @@ __global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs
     }
   } else {
     const double dt = (MODE == 1 && io.dt_out) ? dt_fused : dt_in;
+    // the combination with explicit fused multiply-adds, so that every
+    // variant of the kernel (with or without records) rounds it the same way
     double uo[NF];
     if constexpr (MODE == 1) {
 #pragma unroll
-      for (int f = 0; f < NF; ++f) uo[f] = q[f] + dt * R[f];
+      for (int f = 0; f < NF; ++f) uo[f] = fma(dt, R[f], q[f]);
     } else if constexpr (UN_LDS) {
       // U^n from the wave's LDS slice (its transfer was waited for before
       // the z-face pass)
       const int w = threadIdx.x >> 6;
 #pragma unroll
-      for (int f = 0; f < NF; ++f) uo[f] = A.rk_a * un_lds[w][f][node] + A.rk_b * (q[f] + dt * R[f]);
+      for (int f = 0; f < NF; ++f) uo[f] = fma(A.rk_a, un_lds[w][f][node], A.rk_b * fma(dt, R[f], q[f]));
     } else {
 #pragma unroll
-      for (int f = 0; f < NF; ++f) uo[f] = A.rk_a * io.Un[f * fs + o] + A.rk_b * (q[f] + dt * R[f]);
+      for (int f = 0; f < NF; ++f) uo[f] = fma(A.rk_a, io.Un[f * fs + o], A.rk_b * fma(dt, R[f], q[f]));
     }
     if (valid) {
 #pragma unroll
@@ -1725,7 +1728,7 @@ static __global__ __attribute__((unused)) __launch_bounds__(FIN_THREADS) void k_
   reduce_slots<REC, FIN_THREADS>(rec, 0, n, red);
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double rate = rate_of(red[R_WAVE], red[R_NU], GammaEps, dim, hmin);
+    const double rate = rate_of(red[R_WAVE], red[R_NU], GammaEps, 16.0 * dim, hmin);
     const double d = dt_fixed ? *dt_fixed : cfl / rate;
     if (dt) *dt = d;
     if (t) *t += d;
@@ -1745,13 +1748,13 @@ static __global__ __attribute__((unused)) __launch_bounds__(FIN_THREADS) void k_
 // Final reduction of rate records (time step only): *dt = cfl / rate (or
 // *dt_fixed), *t += dt.
 static __global__ __attribute__((unused)) __launch_bounds__(FIN_THREADS) void k_finalize_rate(const double* __restrict__ rec, long long n,
-                                                               double GammaEps, int dim, double hmin, double cfl,
+                                                               double GammaEps, double pdim, double hmin, double cfl,
                                                                const double* dt_fixed, double* dt, double* t) {
   __shared__ double red[RATE];
   reduce_slots<RATE, FIN_THREADS>(rec, 0, n, red);
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double d = dt_fixed ? *dt_fixed : cfl / rate_of(red[R_WAVE], red[R_NU], GammaEps, dim, hmin);
+    const double d = dt_fixed ? *dt_fixed : cfl / rate_of(red[R_WAVE], red[R_NU], GammaEps, pdim, hmin);
     *dt = d;
     if (t) *t += d;
   }

@@ -75,6 +75,7 @@ _SIG = {
     "dg2p_max_dt": ([_vp, ctypes.POINTER(Params), _dp, _d, _dp, _vp, _vp, _vp], _i),
     "dg2p_rk_step": ([_vp, ctypes.POINTER(Params), _dp, _dp, _vp, _vp], _i),
     "dg2p_rk_step_noalloc": ([_vp, ctypes.POINTER(Params), _dp, _dp, _vp], _i),
+    "dg2p_kin_reinit_params": ([_vp, _d, ctypes.POINTER(_d), ctypes.POINTER(_d)], _i),
     "dg2p_noalloc_scratch_bytes": ([], ctypes.c_size_t),
     "dg2p_compute_monitors": ([_vp, ctypes.POINTER(Params), _dp, _d, _dp, _vp, _vp, _vp], _i),
     "dg2p_advance": ([_vp, ctypes.POINTER(Params), _dp, _i, _d, _dp, _dp, _dp, _vp, _d, _vp, _vp, _vp], _i),
@@ -483,8 +484,8 @@ def kin_reinit(mesh, kp, Phi, n_iter, nu, dtau, stream=None):
 
 
 def kin_reinit_params(mesh, cfl=0.1):
-    """(nu_h, dtau): one nodal spacing h / (p+1) and the pseudo step
-    cfl h / (1 + (p+1)^2 d nu_h / h) of unit-speed transport."""
-    h = min((mesh.desc.hi[k] - mesh.desc.lo[k]) / mesh.desc.n_elem[k] for k in range(mesh.dim))
-    nu = h / 4.0
-    return nu, cfl * h / (1.0 + 16.0 * mesh.dim * nu / h)
+    """(nu_h, dtau) of dg2p_kin_reinit_params."""
+    nu, dtau = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.dg2p_kin_reinit_params(mesh.handle, float(cfl), ctypes.byref(nu), ctypes.byref(dtau)),
+           "dg2p_kin_reinit_params")
+    return nu.value, dtau.value

@@ -16,12 +16,13 @@ import torch
 from . import dg2p, workloads
 
 
-def rider_kothe(N, reinit_every=0, reinit_iters=50, time_it=False):
-    """One Rider-Kothe period on N x N elements, p = 3.  Returns a dict with
-    the L1 error, the relative mass error, the step count and (time_it) the
-    elapsed milliseconds of the whole run."""
-    cfg = workloads.kinematic_config("rk2d", n_elem=(N, N))
-    mesh = dg2p.Mesh(2, (N, N), cfg["lo"], cfg["hi"])
+def rider_kothe(N, reinit_every=0, reinit_iters=50, time_it=False, order=3):
+    """One Rider-Kothe period on N x N elements of degree `order` (3 or 1; the
+    re-initialisation is p = 3 only).  Returns a dict with the L1 error, the
+    relative mass error, the step count and (time_it) the elapsed
+    milliseconds of the whole run."""
+    cfg = workloads.kinematic_config("rk2d", n_elem=(N, N), order=order)
+    mesh = dg2p.Mesh(2, (N, N), cfg["lo"], cfg["hi"], order=order)
     phi, psi, u0 = workloads.kinematic_fields(cfg, mesh.node_coords())
     kp = dg2p.make_kin_params(**cfg["kin"])
     P = torch.from_numpy(np.ascontiguousarray(np.stack([phi, psi]))).cuda()

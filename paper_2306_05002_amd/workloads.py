@@ -325,13 +325,14 @@ KIN_NAMES = ("rk2d", "adv2d")
 KIN_FULL_ELEMS = {"rk2d": (16, 16), "adv2d": (16, 16)}
 
 
-def kinematic_config(name, n_elem=None):
-    """Kinematic test cases of the Results section, p = 3 on [0,1]^2, periodic.
+def kinematic_config(name, n_elem=None, order=ORDER):
+    """Kinematic test cases of the Results section, p = 3 (or 1) on [0,1]^2,
+    periodic.
 
     rk2d   Rider-Kothe single vortex: droplet R = 0.15 at (0.5, 0.75),
            u = (sin^2(pi x) sin(2 pi y), -sin(2 pi x) sin^2(pi y)) cos(pi t / 4),
-           one period T = 4, Gamma = 1, eps = h / 2 (half the element size,
-           i.e. two nodal spacings at p = 3)
+           one period T = 4, Gamma = 1, eps = 2 h / (p + 1): two nodal
+           spacings (h / 2 at p = 3, the element size h at p = 1)
     adv2d  linear advection of a droplet R = 0.15 at (0.5, 0.5) by u = (1, 0)
            for one period, fixed eps = 0.05, Gamma = 1
     """
@@ -339,10 +340,10 @@ def kinematic_config(name, n_elem=None):
         raise KeyError(name)
     n_elem = tuple(n_elem) if n_elem is not None else KIN_FULL_ELEMS[name]
     h = 1.0 / n_elem[0]
-    cfg = dict(name=name, dim=2, order=ORDER, n_elem=n_elem, lo=(0.0, 0.0), hi=(1.0, 1.0),
+    cfg = dict(name=name, dim=2, order=order, n_elem=n_elem, lo=(0.0, 0.0), hi=(1.0, 1.0),
                bc=[("periodic", "periodic")] * 2, cfl=0.1)
     if name == "rk2d":
-        cfg.update(kin=dict(Gamma=1.0, eps=0.5 * h, c_ip=1.0, grad_reg=1e-12, period=4.0),
+        cfg.update(kin=dict(Gamma=1.0, eps=2.0 * h / (order + 1), c_ip=1.0, grad_reg=1e-12, period=4.0),
                    t_end=4.0, centre=(0.5, 0.75))
     else:
         cfg.update(kin=dict(Gamma=1.0, eps=0.05, c_ip=1.0, grad_reg=1e-12, period=0.0),

@@ -138,3 +138,16 @@ def test_noalloc_step_refuses_oversized_mesh_before_any_device_call():
     assert "static scratch" in dg2p._lib.dg2p_last_error().decode()
     st = dg2p._lib.dg2p_rk_step_noalloc(mesh.handle, ctypes.byref(P), None, fake, None)
     assert st == dg2p.EINVAL
+
+
+@pytest.mark.parametrize("n_elem,hi", [((16, 16), (1.0, 1.0)), ((8, 12), (2.0, 1.0))])
+def test_kin_reinit_params_match_the_oracle_reading(n_elem, hi):
+    """dg2p_kin_reinit_params (host arithmetic in the library) and the
+    oracle's reinit_params implement the same reading independently:
+    nu = h_min / (p+1), dtau = 0.1 h_min / (1 + (p+1)^2 d nu / h_min)."""
+    from oracle import kinematic as K
+    mesh = dg2p.Mesh(2, n_elem, (0.0, 0.0), hi)
+    om = oracle.OracleMesh(2, 3, n_elem, (0.0, 0.0), hi)
+    nu, dtau = dg2p.kin_reinit_params(mesh)
+    onu, odtau = K.reinit_params(om)
+    assert abs(nu - onu) <= 1e-15 * onu and abs(dtau - odtau) <= 1e-15 * odtau

@@ -31,25 +31,26 @@ def _T(a):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64)
 
 
-def case(name, ne):
+def case(name, ne, order=3):
     """(oracle mesh, KinParams, Phi0, u0, library mesh, library params) of a
-    kinematic workload, or of a d-dimensional constant-velocity slab/box."""
+    kinematic workload, or of a d-dimensional constant-velocity slab/box, at
+    polynomial degree `order`."""
     dg = _dg()
     if name in workloads.KIN_NAMES:
-        cfg = workloads.kinematic_config(name, n_elem=ne)
-        om = oracle.OracleMesh(2, 3, ne, cfg["lo"], cfg["hi"], cfg["bc"])
+        cfg = workloads.kinematic_config(name, n_elem=ne, order=order)
+        om = oracle.OracleMesh(2, order, ne, cfg["lo"], cfg["hi"], cfg["bc"])
         phi, psi, u0 = workloads.kinematic_fields(cfg, om.node_coords().numpy())
         kin = cfg["kin"]
     else:  # "box<d>": smooth periodic fields, uniform velocity
         d = len(ne)
-        om = oracle.OracleMesh(d, 3, ne, (0.0,) * d, (1.0,) * d)
+        om = oracle.OracleMesh(d, order, ne, (0.0,) * d, (1.0,) * d)
         X = om.node_coords().numpy()
         psi = 0.2 * np.prod([np.cos(2 * math.pi * X[k]) for k in range(d)], axis=0) + 0.05
         kin = dict(Gamma=0.8, eps=0.03, c_ip=1.0, grad_reg=1e-12, period=0.0)
         phi = 1.0 / (1.0 + np.exp(-psi / kin["eps"]))
         u0 = np.stack([np.full_like(psi, (0.7, -0.4, 0.3)[k]) for k in range(d)])
     kp = K.KinParams(**kin)
-    mesh = dg.Mesh(om.d, ne, om.lo, om.hi)
+    mesh = dg.Mesh(om.d, ne, om.lo, om.hi, order=order)
     lkp = dg.make_kin_params(**kin)
     return om, kp, torch.stack([_T(phi), _T(psi)]), _T(u0), mesh, lkp
 
@@ -58,13 +59,15 @@ def rel_err(a, b):
     return [float((a[f] - b[f]).abs().max()) / max(float(b[f].abs().max()), 1e-300) for f in range(a.shape[0])]
 
 
-KIN_RHS = [("rk2d", (16, 16), 0.7), ("rk2d", (5, 3), 1.3), ("rk2d", (1, 1), 0.0), ("adv2d", (8, 8), 0.2),
-           ("box1", (13,), 0.0), ("box3", (3, 2, 4), 0.0)]
+KIN_RHS = [("rk2d", (16, 16), 0.7, 3), ("rk2d", (5, 3), 1.3, 3), ("rk2d", (1, 1), 0.0, 3), ("adv2d", (8, 8), 0.2, 3),
+           ("box1", (13,), 0.0, 3), ("box3", (3, 2, 4), 0.0, 3),
+           ("rk2d", (32, 32), 0.7, 1), ("rk2d", (5, 3), 1.3, 1), ("rk2d", (1, 1), 0.0, 1), ("rk2d", (2, 1), 0.3, 1),
+           ("adv2d", (9, 8), 0.2, 1), ("box1", (13,), 0.0, 1), ("box3", (3, 2, 4), 0.0, 1)]
 
 
-@pytest.mark.parametrize("name,ne,t", KIN_RHS)
-def test_kin_rhs_parity(name, ne, t):
-    om, kp, Phi, u0, mesh, lkp = case(name, ne)
+@pytest.mark.parametrize("name,ne,t,order", KIN_RHS)
+def test_kin_rhs_parity(name, ne, t, order):
+    om, kp, Phi, u0, mesh, lkp = case(name, ne, order)
     Ro = K.kin_rhs(Phi, K.velocity(u0, t, kp), om, kp)
     Rg = _dg().kin_rhs(mesh, lkp, Phi.cuda(), u0.cuda(), t).cpu()
     errs = rel_err(Rg, Ro)
@@ -72,9 +75,10 @@ def test_kin_rhs_parity(name, ne, t):
     assert max(errs) <= TOL, errs
 
 
-@pytest.mark.parametrize("name,ne", [("rk2d", (6, 5)), ("adv2d", (7, 4)), ("box3", (2, 3, 2))])
-def test_kin_rk4_parity(name, ne):
-    om, kp, Phi, u0, mesh, lkp = case(name, ne)
+@pytest.mark.parametrize("name,ne,order", [("rk2d", (6, 5), 3), ("adv2d", (7, 4), 3), ("box3", (2, 3, 2), 3),
+                                           ("rk2d", (12, 10), 1), ("box1", (9,), 1), ("box3", (4, 3, 2), 1)])
+def test_kin_rk4_parity(name, ne, order):
+    om, kp, Phi, u0, mesh, lkp = case(name, ne, order)
     dt, t0, n = 0.002, 0.4, 4
     Po = Phi
     for s in range(n):
@@ -85,9 +89,10 @@ def test_kin_rk4_parity(name, ne):
     assert max(errs) <= TOL, errs
 
 
-@pytest.mark.parametrize("name,ne", [("rk2d", (16, 16)), ("rk2d", (7, 9)), ("box1", (10,))])
-def test_kin_max_dt_and_errors(name, ne):
-    om, kp, Phi, u0, mesh, lkp = case(name, ne)
+@pytest.mark.parametrize("name,ne,order", [("rk2d", (16, 16), 3), ("rk2d", (7, 9), 3), ("box1", (10,), 3),
+                                           ("rk2d", (33, 32), 1), ("box1", (10,), 1), ("box3", (3, 5, 2), 1)])
+def test_kin_max_dt_and_errors(name, ne, order):
+    om, kp, Phi, u0, mesh, lkp = case(name, ne, order)
     dg = _dg()
     dtg = float(dg.kin_max_dt(mesh, lkp, u0.cuda(), cfl=0.1).cpu())
     dto = K.max_dt(u0, om, kp, cfl=0.1)
@@ -112,6 +117,12 @@ def test_kin_rejects_unsupported():
     with pytest.raises(dg.Dg2pError) as ei:
         dg.kin_rhs(mp, dg.make_kin_params(eps=0.0), Phi, u0, 0.0)
     assert ei.value.status == dg.EINVAL
+    # p = 1: kinematic transport only (no re-initialisation, no two-phase model)
+    m1 = dg.Mesh(2, (4, 4), (0, 0), (1, 1), order=1)
+    P1 = torch.zeros(2, m1.E, m1.nn, dtype=torch.float64, device="cuda")
+    with pytest.raises(dg.Dg2pError) as ei:
+        dg.kin_reinit(m1, dg.make_kin_params(), P1, 2, 0.1, 0.01)
+    assert ei.value.status == dg.EUNSUPPORTED
 
 
 @pytest.mark.parametrize("name,ne", [("rk2d", (6, 5)), ("box1", (13,)), ("box3", (2, 3, 2))])
@@ -130,19 +141,19 @@ def test_kin_reinit_parity(name, ne):
     assert err <= TOL, err
 
 
-@pytest.mark.parametrize("reinit", [False, True])
-def test_rider_kothe_full_period_matches_oracle_run(reinit):
+@pytest.mark.parametrize("N,order,reinit", [(16, 3, False), (16, 3, True), (32, 1, False)])
+def test_rider_kothe_full_period_matches_oracle_run(N, order, reinit):
     """One full Rider-Kothe period at 16 x 16 p3 (64^2 DOF, ~11 000 RK4
-    steps; with re-initialisation of psi every 2000 steps) on the GPU against
-    the oracle's stored run of the same problem (tests/golden/, written by
-    make_kinematic_golden.py)."""
-    name = "rk2d_16x16_p3_reinit.json" if reinit else "rk2d_16x16_p3.json"
+    steps; with re-initialisation of psi every 2000 steps) and at 32 x 32 p1
+    on the GPU against the oracle's stored run of the same problem
+    (tests/golden/, written by make_kinematic_golden.py)."""
+    name = "rk2d_%dx%d_p%d%s.json" % (N, N, order, "_reinit" if reinit else "")
     path = os.path.join(HERE, "golden", name)
     if not os.path.exists(path):
         pytest.skip("oracle golden run not generated")
     gold = json.load(open(path))
     from paper_2306_05002_amd import kinematic
-    r = kinematic.rider_kothe(16, reinit_every=2000 if reinit else 0)
+    r = kinematic.rider_kothe(N, reinit_every=2000 if reinit else 0, order=order)
     assert r["steps"] == gold["steps"]
     print("L1", r["l1"], gold["l1"], "E_m", r["mass_error"], gold["mass_error"])
     assert abs(r["l1"] - gold["l1"]) <= 1e-9 * gold["l1"]
