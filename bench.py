@@ -158,24 +158,33 @@ def cpu_baseline(cfg, pf, seconds):
 # L1 errors of the paper's Rider-Kothe table (quadrilateral mesh, p = 3) at
 # 64^2, 128^2, 256^2 degrees of freedom, i.e. 16^2, 32^2, 64^2 elements
 PAPER_RK_L1_P3 = {16: 1.75e-2, 32: 4.83e-3, 64: 1.23e-3}
+PAPER_RK_L1_P1 = {32: 2.22e-2, 64: 8.71e-3, 128: 3.31e-3}
 
 
 def kinematic_section():
     """Rider-Kothe single vortex, one full period, classical RK4, on the
-    library's kinematic mode at three resolutions, without and with the
-    level-set re-initialisation (50 pseudo-time iterations every 2000 steps):
-    L1 error, relative mass error and the kinematic stage throughput."""
+    library's kinematic mode at the paper's six cells (64^2, 128^2, 256^2
+    nodes at p = 3 and p = 1): L1 error and relative mass error with the
+    nodal analytic velocity, the same with the stream-function velocity
+    (discretely divergence free), at p = 3 also with the level-set
+    re-initialisation (50 pseudo-time iterations every 2000 steps), and the
+    kinematic stage throughput."""
     from paper_2306_05002_amd import kinematic
     rows = []
-    for N in sorted(PAPER_RK_L1_P3):
-        r0 = kinematic.rider_kothe(N, time_it=True)
-        r1 = kinematic.rider_kothe(N, reinit_every=2000)
-        rows.append({"elements": [N, N], "dof": f"{4 * N}^2", "steps": r0["steps"],
-                     "l1": r0["l1"], "l1_reinit": r1["l1"], "l1_paper": PAPER_RK_L1_P3[N],
-                     "mass_error": r0["mass_error"], "mass_error_reinit": r1["mass_error"],
-                     "reinit_calls": r1["reinit"], "ms_per_step": r0["ms"] / r0["steps"],
-                     "value": 4.0 * r0["dof"] * r0["steps"] / (r0["ms"] * 1e-3)})
-    return {"workload": "rk2d: Rider-Kothe vortex, [0,1]^2 periodic, p=3, eps=h/2, Gamma=1, T=4, RK4, CFL 0.1",
+    for order, table in ((3, PAPER_RK_L1_P3), (1, PAPER_RK_L1_P1)):
+        for N in sorted(table):
+            r0 = kinematic.rider_kothe(N, time_it=True, order=order)
+            rs = kinematic.rider_kothe(N, order=order, velocity="stream")
+            row = {"order": order, "elements": [N, N], "dof": f"{(order + 1) * N}^2", "steps": r0["steps"],
+                   "l1": r0["l1"], "l1_paper": table[N], "mass_error": r0["mass_error"],
+                   "l1_stream_velocity": rs["l1"], "mass_error_stream_velocity": rs["mass_error"]}
+            if order == 3:
+                r1 = kinematic.rider_kothe(N, reinit_every=2000, order=order)
+                row.update(l1_reinit=r1["l1"], mass_error_reinit=r1["mass_error"], reinit_calls=r1["reinit"])
+            row.update(ms_per_step=r0["ms"] / r0["steps"], value=4.0 * r0["dof"] * r0["steps"] / (r0["ms"] * 1e-3))
+            rows.append(row)
+    return {"workload": "rk2d: Rider-Kothe vortex, [0,1]^2 periodic, p=3 and p=1, eps=2h/(p+1), Gamma=1, T=4, "
+                        "RK4, CFL 0.1",
             "unit": "DOF-updates/s", "runs": rows}
 
 

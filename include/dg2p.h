@@ -37,7 +37,10 @@
  *     synchronously and nothing is launched; dg2p_last_error() gives the
  *     detail (thread-local).  Non-physical states are never fatal inside a
  *     call: they are counted in dg2p_monitors.nonphys.
- *   - Only polynomial order p = 3 is implemented (DG2P_EUNSUPPORTED else).
+ *   - The two-phase model is implemented at polynomial order p = 3; the
+ *     kinematic mode (dg2p_kin_*, re-initialisation excepted) also at p = 1
+ *     (DG2P_EUNSUPPORTED else).  Nodes per element n = (p+1)^d, node
+ *     j = sum_k a_k (p+1)^k; the layouts below write 4^d for p = 3.
  */
 #ifndef DG2P_H
 #define DG2P_H
@@ -103,7 +106,7 @@ typedef enum {
  * Galerkin discretisation").  Entries beyond `dim` are ignored. */
 typedef struct {
   int dim;                   /* 1, 2 or 3 */
-  int order;                 /* polynomial degree p (must be 3) */
+  int order;                 /* polynomial degree p: 3, or 1 (kinematic mode only) */
   int n_elem[3];             /* elements per axis, >= 1 */
   double lo[3], hi[3];       /* box corners, hi > lo */
   int bc[3][2];              /* dg2p_bc per axis and side (0 = low, 1 = high) */
@@ -153,14 +156,14 @@ int dg2p_create_mesh(const dg2p_mesh_desc* desc /*host*/, dg2p_mesh* out /*host*
 /* Release a mesh handle (NULL is accepted). */
 int dg2p_destroy_mesh(dg2p_mesh m);
 
-/* Field count N_f = d + 5, element count E and nodes per element 4^d (host outputs). */
+/* Field count N_f = d + 5, element count E and nodes per element n = (p+1)^d (host outputs). */
 int dg2p_layout(dg2p_mesh m, int* n_fields, long long* n_elem, int* nodes_per_elem);
 
-/* Physical GLL node coordinates, host array xyz[d][E][4^d] (caller-owned). */
+/* Physical GLL node coordinates, host array xyz[d][E][n] (caller-owned). */
 int dg2p_node_coords(dg2p_mesh m, double* xyz /*host*/);
 
-/* Diagonal mass-matrix weights W_j = prod_k w_{a_k} J_k of the 4^d nodes of
- * an element (identical for every element), host array W[4^d]. */
+/* Diagonal mass-matrix weights W_j = prod_k w_{a_k} J_k of the n nodes of
+ * an element (identical for every element), host array W[n]. */
 int dg2p_node_weights(dg2p_mesh m, double* W /*host*/);
 
 /* Bytes of device workspace that `op` needs for this mesh and parameters. */
@@ -285,9 +288,10 @@ int dg2p_compute_monitors(dg2p_mesh m, const dg2p_params* p /*host*/, const doub
  * u in place of rho u / rho; the face speed is max |u.m| over both traces
  * (there is no sound speed), which makes the hat/tilde correction the upwind
  * flux.  Classical RK4 in time (the paper's integrator for these tests).
- * Periodic meshes only (EUNSUPPORTED else); FP64.
- *   state    Phi[2][E][4^d]: Phi[0] = phi, Phi[1] = psi
- *   velocity u0[d][E][4^d]: nodal amplitude u0 (device)                      */
+ * Periodic meshes only (EUNSUPPORTED else); FP64; p = 3 or p = 1 (the
+ * paper's two orders of the Rider-Kothe study; n = (p+1)^d nodes per element).
+ *   state    Phi[2][E][n]: Phi[0] = phi, Phi[1] = psi
+ *   velocity u0[d][E][n]: nodal amplitude u0 (device)                        */
 typedef struct {
   double Gamma, eps;   /* Allen-Cahn velocity scale and thickness (Gamma >= 0, eps > 0) */
   double c_ip;         /* interior-penalty constant (> 0) */
@@ -299,7 +303,7 @@ typedef struct {
  * dg2p_kin_reinit) or _KIN_AUX. */
 int dg2p_kin_workspace_size(dg2p_mesh m, int op, size_t* bytes /*host*/);
 
-/* R = dPhi/dt at time t (host scalar), [2][E][4^d]; Phi, u0, R device, R may
+/* R = dPhi/dt at time t (host scalar), [2][E][n]; Phi, u0, R device, R may
  * not alias Phi.  work: DG2P_OP_KIN_RHS bytes. */
 int dg2p_kin_rhs(dg2p_mesh m, const dg2p_kin_params* kp /*host*/, const double* Phi /*device*/,
                  const double* u0 /*device*/, double t, double* R /*device*/, void* work /*device*/,
@@ -321,7 +325,7 @@ int dg2p_kin_rk4(dg2p_mesh m, const dg2p_kin_params* kp /*host*/, double* Phi /*
  * (|grad psi0| regularised by grad_reg) and the diffusive flux discretised
  * with the symmetric interior penalty (coefficient nu, penalty
  * c_ip nu (p+1)^2 / h).  The source sign is the one that relaxes |grad psi|
- * towards 1.  Phi[0] is unchanged.  work: DG2P_OP_KIN_RK4 bytes. */
+ * towards 1.  Phi[0] is unchanged.  p = 3 only.  work: DG2P_OP_KIN_RK4 bytes. */
 int dg2p_kin_reinit(dg2p_mesh m, const dg2p_kin_params* kp /*host*/, double* Phi /*device, in/out*/, int n_iter,
                     double nu, double dtau, void* work /*device*/, void* stream);
 
@@ -341,9 +345,23 @@ int dg2p_kin_max_dt(dg2p_mesh m, const dg2p_kin_params* kp /*host*/, const doubl
 /* GLL-quadrature integrals for the L1 error and the relative mass error of
  * the Rider-Kothe study: out[0] = int |phi - phi0|, out[1] = int (phi - phi0),
  * out[2] = int phi0 (device array of 3; fixed summation order).  phi, phi0:
- * device [E][4^d].  work: DG2P_OP_KIN_AUX bytes. */
+ * device [E][n].  work: DG2P_OP_KIN_AUX bytes. */
 int dg2p_kin_errors(dg2p_mesh m, const double* phi /*device*/, const double* phi0 /*device*/,
                     double* out /*device*/, void* work /*device*/, void* stream);
+
+/* Velocity amplitude of a 2D kinematic run from a nodal stream function
+ * (Results, "Rider-Kothe vortex": the prescribed field is divergence free;
+ * this is one representation of it on the mesh): u0 = (dS/dy, -dS/dx), each
+ * derivative the element-local derivative of the nodal interpolant of S.
+ * The discrete divergence D_x u0_x + D_y u0_y is then zero at every node
+ * (the two element-local derivatives commute), and u0.m is continuous across
+ * faces (the tangential derivative of the continuous trace of S), so the
+ * transport conserves int phi to rounding; the nodally interpolated analytic
+ * field conserves it only up to sum_j W_j phi_j (div_h u0)_j.  S: device
+ * [E][n]; u0: device [2][E][n], may not alias S.  dim = 2 only (EUNSUPPORTED
+ * else); no workspace; p = 3 or 1. */
+int dg2p_kin_velocity_from_stream(dg2p_mesh m, const double* S /*device*/, double* u0 /*device, out*/,
+                                  void* stream);
 
 /* Kernel kinds of the timing facility. */
 typedef enum {

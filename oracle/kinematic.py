@@ -128,6 +128,19 @@ def velocity(u0, t, kp):
     return u0 * time_factor(t, kp)
 
 
+def velocity_from_stream(S, mesh):
+    """2D velocity amplitude u0 = (dS/dy, -dS/dx) from a nodal stream
+    function S [element, node], with the broken (element-local) derivatives:
+    one representation on the mesh of the divergence-free prescribed field of
+    the Rider-Kothe study.  Its discrete divergence vanishes node by node and
+    its normal component is continuous across faces."""
+    n = mesh.n
+    F = S.reshape(S.shape[0], n, n)
+    ux = _dk(F, 1, mesh)
+    uy = -_dk(F, 0, mesh)
+    return torch.stack([ux.reshape(S.shape), uy.reshape(S.shape)])
+
+
 def rk4_step(Phi, t, dt, u0, mesh, kp, rhs_fn=None):
     """Classical fourth-order Runge-Kutta step from time t.
     ``rhs_fn(Phi, t)`` replaces the DG residual (used to pin the scheme)."""

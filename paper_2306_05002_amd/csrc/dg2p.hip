@@ -1139,6 +1139,26 @@ int dg2p_kin_reinit_params(dg2p_mesh m, double cfl, double* nu, double* dtau) {
   return DG2P_OK;
 }
 
+int dg2p_kin_velocity_from_stream(dg2p_mesh m, const double* S, double* u0, void* stream) {
+  g_last_error.clear();
+  if (!m || !S || !u0) return fail(DG2P_EINVAL, "mesh, S and u0 must be non-NULL");
+  if (S == u0) return fail(DG2P_EINVAL, "u0 may not alias S");
+  if (m->dim != 2) return fail(DG2P_EUNSUPPORTED, "the stream-function velocity is two-dimensional");
+  CurlArgs C{};
+  const int n = m->desc.order + 1;
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) C.D[a][b] = m->D[a][b];
+  C.Jinv[0] = 1.0 / m->J[0];
+  C.Jinv[1] = 1.0 / m->J[1];
+  C.n = n;
+  C.E = m->E;
+  const long long total = m->E * m->nn;
+  if (total == 0) return DG2P_OK;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_kin_curl, dim3((unsigned)((total + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, C, S, u0);
+  return hip_check(hipGetLastError(), "kin_velocity_from_stream launch");
+}
+
 int dg2p_kin_max_dt(dg2p_mesh m, const dg2p_kin_params* kp, const double* u0, double cfl, double* dt, void* work,
                     void* stream) {
   g_last_error.clear();

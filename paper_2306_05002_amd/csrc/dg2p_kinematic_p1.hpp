@@ -208,3 +208,36 @@ __global__ __launch_bounds__(BLOCK) void k_kin1_errors(KArgs A, long long n, con
 }
 
 }  // namespace dg2p
+
+namespace dg2p {
+
+// Velocity amplitude from a nodal stream function S (2D, either order):
+// u0 = (dS/dy, -dS/dx) with the element-local nodal derivatives, one thread
+// per node.  D is the GLL derivative matrix of the mesh's order (n x n used).
+struct CurlArgs {
+  double D[4][4];
+  double Jinv[2];
+  int n;
+  long long E;
+};
+
+__global__ __launch_bounds__(BLOCK) void k_kin_curl(CurlArgs C, const double* __restrict__ S,
+                                                    double* __restrict__ u0) {
+  const int n = C.n, nn = n * n;
+  const long long total = C.E * nn;
+  const long long i = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= total) return;
+  const long long e = i / nn;
+  const int j = (int)(i - e * nn);
+  const int ax = j % n, ay = j / n;
+  const double* s = S + e * nn;
+  double dx = 0.0, dy = 0.0;
+  for (int b = 0; b < n; ++b) {
+    dx = fma(C.D[ax][b], s[b + n * ay], dx);
+    dy = fma(C.D[ay][b], s[ax + n * b], dy);
+  }
+  u0[i] = dy * C.Jinv[1];
+  u0[total + i] = -(dx * C.Jinv[0]);
+}
+
+}  // namespace dg2p

@@ -91,6 +91,7 @@ _SIG = {
     "dg2p_kin_max_dt": ([_vp, ctypes.POINTER(KinParams), _dp, _d, _dp, _vp, _vp], _i),
     "dg2p_kin_reinit": ([_vp, ctypes.POINTER(KinParams), _dp, _i, _d, _d, _vp, _vp], _i),
     "dg2p_kin_errors": ([_vp, _dp, _dp, _dp, _vp, _vp], _i),
+    "dg2p_kin_velocity_from_stream": ([_vp, _dp, _dp, _vp], _i),
     "dg2p_timing_enable": ([_i], _i),
     "dg2p_timing_read": ([_i, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_longlong)], _i),
 }
@@ -471,6 +472,17 @@ def kin_errors(mesh, phi, phi0, stream=None):
     _check(_lib.dg2p_kin_errors(mesh.handle, _ptr(phi), _ptr(phi0), _ptr(out), ws, _stream(stream)),
            "dg2p_kin_errors")
     return out
+
+
+def kin_velocity_from_stream(mesh, S, stream=None):
+    """Velocity amplitude u0 = (dS/dy, -dS/dx) [2, E, nn] of a nodal stream
+    function S [E, nn] (2D; element-local derivatives)."""
+    if S.dtype != torch.float64 or not S.is_cuda or not S.is_contiguous() or tuple(S.shape) != (mesh.E, mesh.nn):
+        raise ValueError("S must be a contiguous float64 CUDA tensor of shape (E, nn)")
+    u0 = torch.empty(2, mesh.E, mesh.nn, dtype=torch.float64, device=S.device)
+    _check(_lib.dg2p_kin_velocity_from_stream(mesh.handle, _ptr(S), _ptr(u0), _stream(stream)),
+           "dg2p_kin_velocity_from_stream")
+    return u0
 
 
 def kin_reinit(mesh, kp, Phi, n_iter, nu, dtau, stream=None):

@@ -16,22 +16,30 @@ import torch
 from . import dg2p, workloads
 
 
-def rider_kothe(N, reinit_every=0, reinit_iters=50, time_it=False, order=3):
+def rider_kothe(N, reinit_every=0, reinit_iters=50, time_it=False, order=3, velocity="nodal"):
     """One Rider-Kothe period on N x N elements of degree `order` (3 or 1; the
-    re-initialisation is p = 3 only).  Returns a dict with the L1 error, the
-    relative mass error, the step count and (time_it) the elapsed
-    milliseconds of the whole run."""
+    re-initialisation is p = 3 only).  velocity "nodal": the analytic field
+    at the nodes; "stream": the field from the nodal stream function
+    (dg2p_kin_velocity_from_stream, discretely divergence free).  Returns a
+    dict with the L1 error, the relative mass error, the step count and
+    (time_it) the elapsed milliseconds of the whole run."""
     cfg = workloads.kinematic_config("rk2d", n_elem=(N, N), order=order)
     mesh = dg2p.Mesh(2, (N, N), cfg["lo"], cfg["hi"], order=order)
     phi, psi, u0 = workloads.kinematic_fields(cfg, mesh.node_coords())
     kp = dg2p.make_kin_params(**cfg["kin"])
     P = torch.from_numpy(np.ascontiguousarray(np.stack([phi, psi]))).cuda()
     P0 = P[0].clone()
-    u0d = torch.from_numpy(np.ascontiguousarray(u0)).cuda()
+    if velocity == "stream":
+        S = torch.from_numpy(np.ascontiguousarray(workloads.kinematic_stream(cfg, mesh.node_coords()))).cuda()
+        u0d = dg2p.kin_velocity_from_stream(mesh, S)
+    elif velocity == "nodal":
+        u0d = torch.from_numpy(np.ascontiguousarray(u0)).cuda()
+    else:
+        raise ValueError("velocity must be 'nodal' or 'stream'")
     dt0 = float(dg2p.kin_max_dt(mesh, kp, u0d, cfl=cfg["cfl"]).cpu())
     ns = int(math.ceil(cfg["t_end"] / dt0))
     dt = cfg["t_end"] / ns
-    nu, dtau = dg2p.kin_reinit_params(mesh)
+    nu, dtau = dg2p.kin_reinit_params(mesh) if reinit_every > 0 else (0.0, 0.0)
     e0 = e1 = None
     if time_it:
         torch.cuda.synchronize()

@@ -365,3 +365,12 @@ def kinematic_fields(cfg, X):
     else:
         u0 = np.stack([np.ones_like(x), np.zeros_like(x)])
     return phi, psi, u0
+
+
+def kinematic_stream(cfg, X):
+    """Nodal stream function S of the prescribed field, u0 = (dS/dy, -dS/dx):
+    S = sin^2(pi x) sin^2(pi y) / pi for rk2d, S = y for adv2d."""
+    x, y = X[0], X[1]
+    if cfg["name"] == "rk2d":
+        return np.sin(math.pi * x) ** 2 * np.sin(math.pi * y) ** 2 / math.pi
+    return np.array(y, dtype=np.float64, copy=True)

@@ -151,3 +151,29 @@ def test_kin_reinit_params_match_the_oracle_reading(n_elem, hi):
     nu, dtau = dg2p.kin_reinit_params(mesh)
     onu, odtau = K.reinit_params(om)
     assert abs(nu - onu) <= 1e-15 * onu and abs(dtau - odtau) <= 1e-15 * odtau
+
+
+def test_order_one_meshes_and_their_host_checks():
+    """p = 1 meshes (kinematic mode): four nodes per 2D element at the
+    corners, weights J_x J_y; the two-phase entry points and the
+    re-initialisation refuse them on the host, and the stream-function
+    velocity refuses non-2D meshes and aliasing before any device call."""
+    m1 = dg2p.Mesh(2, (5, 4), (0.0, 0.0), (1.0, 1.0), order=1)
+    assert (m1.nf, m1.E, m1.nn) == (7, 20, 4)
+    om = oracle.OracleMesh(2, 1, (5, 4), (0.0, 0.0), (1.0, 1.0))
+    assert np.array_equal(m1.node_coords(), om.node_coords().numpy())
+    W = m1.node_weights()
+    assert np.allclose(np.asarray(W), om.node_weights().numpy(), rtol=0, atol=1e-17)
+    fake = ctypes.c_void_p(1 << 20)
+    P = dg2p.make_params(workloads.config("drop2d")["params"])
+    st = dg2p._lib.dg2p_rhs(m1.handle, ctypes.byref(P), fake, ctypes.c_void_p(2 << 20), fake, None)
+    assert st == dg2p.EUNSUPPORTED
+    kp = dg2p.make_kin_params()
+    st = dg2p._lib.dg2p_kin_reinit(m1.handle, ctypes.byref(kp), fake, 2, ctypes.c_double(0.1),
+                                   ctypes.c_double(0.01), fake, None)
+    assert st == dg2p.EUNSUPPORTED
+    m3 = dg2p.Mesh(3, (2, 2, 2), (0.0,) * 3, (1.0,) * 3)
+    assert dg2p._lib.dg2p_kin_velocity_from_stream(m3.handle, fake, ctypes.c_void_p(2 << 20), None) \
+        == dg2p.EUNSUPPORTED
+    assert dg2p._lib.dg2p_kin_velocity_from_stream(m1.handle, fake, fake, None) == dg2p.EINVAL
+    assert dg2p._lib.dg2p_kin_velocity_from_stream(m1.handle, None, fake, None) == dg2p.EINVAL

@@ -158,3 +158,41 @@ def test_rider_kothe_full_period_matches_oracle_run(N, order, reinit):
     print("L1", r["l1"], gold["l1"], "E_m", r["mass_error"], gold["mass_error"])
     assert abs(r["l1"] - gold["l1"]) <= 1e-9 * gold["l1"]
     assert abs(r["mass_error"] - gold["mass_error"]) <= 1e-6 * abs(gold["mass_error"]) + 1e-13
+
+
+@pytest.mark.parametrize("order,ne", [(3, (7, 5)), (1, (9, 4)), (3, (1, 1))])
+def test_velocity_from_stream_parity(order, ne):
+    """dg2p_kin_velocity_from_stream against the oracle's broken derivatives."""
+    cfg = workloads.kinematic_config("rk2d", n_elem=ne, order=order)
+    om = oracle.OracleMesh(2, order, ne, cfg["lo"], cfg["hi"], cfg["bc"])
+    S = _T(workloads.kinematic_stream(cfg, om.node_coords().numpy()))
+    want = K.velocity_from_stream(S, om)
+    mesh = _dg().Mesh(2, ne, cfg["lo"], cfg["hi"], order=order)
+    got = _dg().kin_velocity_from_stream(mesh, S.cuda().contiguous()).cpu()
+    assert float((got - want).abs().max()) <= 1e-13 * float(want.abs().max())
+
+
+@pytest.mark.parametrize("order,N", [(3, 16), (1, 32)])
+def test_stream_velocity_conserves_mass_to_rounding(order, N):
+    """With the stream-function velocity the discrete divergence vanishes, so
+    int phi is an invariant of the residual and of RK4: 300 steps of the
+    Rider-Kothe run keep E_m at rounding level, where the nodal field's
+    discrete divergence moves it by orders of magnitude more."""
+    dg = _dg()
+    cfg = workloads.kinematic_config("rk2d", n_elem=(N, N), order=order)
+    mesh = dg.Mesh(2, (N, N), cfg["lo"], cfg["hi"], order=order)
+    X = mesh.node_coords()
+    phi, psi, u0 = workloads.kinematic_fields(cfg, X)
+    kp = dg.make_kin_params(**cfg["kin"])
+    S = _T(workloads.kinematic_stream(cfg, X)).cuda()
+    out = {}
+    for rep, u in (("stream", dg.kin_velocity_from_stream(mesh, S)), ("nodal", _T(u0).cuda())):
+        P = torch.stack([_T(phi), _T(psi)]).cuda().contiguous()
+        P0 = P[0].clone()
+        dt = float(dg.kin_max_dt(mesh, kp, u, cfl=0.1).cpu())
+        dg.kin_rk4(mesh, kp, P, u, 300, 0.0, dt)
+        e = dg.kin_errors(mesh, P[0].contiguous(), P0).cpu().tolist()
+        out[rep] = abs(e[1] / e[2])
+    print(order, N, out)
+    assert out["stream"] < 1e-13
+    assert out["nodal"] > 1e3 * out["stream"]

@@ -295,3 +295,53 @@ def test_reinit_converges_to_distance_near_interface():
     for x0 in (0.25, 0.75):
         i = int(torch.argmin(torch.abs(xs - x0)))
         assert abs(float(ps[i])) < 1e-6
+
+
+# ---- velocity representation and the mass balance ---------------------------------
+
+@pytest.mark.parametrize("p", [3, 1])
+def test_velocity_from_stream_differentiates_polynomials_exactly(p):
+    """A stream function of degree <= p per axis is interpolated exactly, so
+    u0 = (dS/dy, -dS/dx) is exact at the nodes (fails on swapped axes, a
+    wrong sign or a wrong Jacobian)."""
+    mesh = oracle.OracleMesh(2, p, (3, 4), (0.0, -1.0), (1.5, 1.0))
+    x, y = mesh.node_coords()
+    if p == 3:
+        S = x ** 3 * y ** 2 + 2 * x * y ** 3 - y
+        want = torch.stack([2 * x ** 3 * y + 6 * x * y ** 2 - 1, -(3 * x ** 2 * y ** 2 + 2 * y ** 3)])
+    else:
+        S = x * y + 3 * x - 2 * y
+        want = torch.stack([x - 2, -(y + 3)])
+    u0 = K.velocity_from_stream(S, mesh)
+    assert float((u0 - want).abs().max()) < 1e-11
+
+
+@pytest.mark.parametrize("p", [3, 1])
+def test_mass_balance_is_the_discrete_divergence_of_the_velocity(p):
+    """Random phi and psi, Gamma > 0, a nodally interpolated velocity field
+    (continuous at the shared face nodes): sum_j W_j R_phi_j equals
+    sum_j W_j phi_j (div_h u)_j to rounding (the upwind face terms, the
+    SIPG a-flux and its symmetric term all cancel in the sum), and is zero to
+    rounding for the stream-function velocity, whose div_h u vanishes.  Fails
+    on a wrong upwind sign, an unpaired face term or a lift factor that does
+    not match the face quadrature."""
+    torch.manual_seed(3)
+    N = 6 if p == 3 else 9
+    mesh = oracle.OracleMesh(2, p, (N, N - 1), (0.0, 0.0), (1.0, 1.0))
+    x, y = mesh.node_coords()
+    kp = K.KinParams(Gamma=0.7, eps=0.04)
+    Phi = torch.stack([torch.rand(mesh.E, mesh.nn), torch.randn(mesh.E, mesh.nn)])
+    W = mesh.node_weights()
+    u_nodal = K.rider_kothe_velocity(torch.stack([x, y]))
+    n = mesh.n
+    div = (K._dk(u_nodal[0].reshape(-1, n, n), 0, mesh) + K._dk(u_nodal[1].reshape(-1, n, n), 1, mesh)).reshape(
+        mesh.E, mesh.nn)
+    R = K.kin_rhs(Phi, u_nodal, mesh, kp)
+    got = float((W * R[0]).sum())
+    want = float((W * Phi[0] * div).sum())
+    scale = float((W * (R[0].abs() + (Phi[0] * div).abs())).sum())
+    assert abs(got - want) < 1e-13 * scale, (got, want)
+    assert abs(want) > 1e-6 * scale            # the nodal field is not discretely divergence free
+    S = torch.sin(math.pi * x) ** 2 * torch.sin(math.pi * y) ** 2 / math.pi
+    Rs = K.kin_rhs(Phi, K.velocity_from_stream(S, mesh), mesh, kp)
+    assert abs(float((W * Rs[0]).sum())) < 1e-13 * float((W * Rs[0].abs()).sum())
