@@ -6,6 +6,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -110,12 +111,16 @@ int check_params(const dg2p_mesh_s* m, const dg2p_params* p) {
 }
 
 
+// Threads per workgroup of the element passes of a mesh (ewg<DIM>()).
+int elem_threads(int dim) { return dim == 3 ? ewg<3>() : (dim == 2 ? ewg<2>() : ewg<1>()); }
+
 KArgs make_args(const dg2p_mesh_s* m, const dg2p_params* p) {
   KArgs A;
   std::memset(&A, 0, sizeof(A));
   A.E = m->E;
   const int epw = 64 >> (2 * m->dim);
-  A.nblocks = (m->E + (long long)(BLOCK / 64) * epw - 1) / ((long long)(BLOCK / 64) * epw);
+  const long long per_wg = (long long)(elem_threads(m->dim) / 64) * epw;  // elements per workgroup
+  A.nblocks = (m->E + per_wg - 1) / per_wg;
   A.xcd_chunk = (A.nblocks + 7) / 8;
   for (int k = 0; k < 3; ++k) {
     A.N[k] = k < m->dim ? m->N[k] : 1;
@@ -213,7 +218,7 @@ size_t state_bytes(const dg2p_mesh_s* m) {
 constexpr long long REC2_MAX = 1024;   // second-level records
 constexpr long long REC_GRID = 1024;   // workgroups of the stand-alone record pass
 long long elem_blocks(const dg2p_mesh_s* m) {
-  const long long per = (long long)(BLOCK / 64) * (64 >> (2 * m->dim));
+  const long long per = (long long)(elem_threads(m->dim) / 64) * (64 >> (2 * m->dim));
   return (m->E + per - 1) / per;
 }
 size_t rec_bytes(const dg2p_mesh_s* m) {
@@ -474,7 +479,7 @@ size_t kin_work_bytes(const dg2p_mesh_s* m, int op) {
 template <int DIM>
 void kin_ingr_d(const KArgs& A, const double* P, double* G, hipStream_t s) {
   TimedLaunch t(DG2P_K_INGREDIENTS, s);
-  hipLaunchKernelGGL(k_kin_ingredients<DIM>, elem_grid(A), dim3(BLOCK), 0, s, A, P, G);
+  hipLaunchKernelGGL(k_kin_ingredients<DIM>, elem_grid(A), dim3(ewg<DIM>()), 0, s, A, P, G);
 }
 void kin_ingr(const dg2p_mesh_s* m, const KArgs& A, const double* P, double* G, hipStream_t s) {
   if (m->desc.order == 1) return;  // the p = 1 kernels differentiate the neighbours themselves
@@ -485,7 +490,7 @@ void kin_ingr(const dg2p_mesh_s* m, const KArgs& A, const double* P, double* G, 
 template <int DIM>
 void kin_stage_d(int mode, const KArgs& A, const KinIO& io, hipStream_t s) {
   TimedLaunch t(DG2P_K_KIN_STAGE, s);
-  const dim3 g = elem_grid(A), b(BLOCK);
+  const dim3 g = elem_grid(A), b(ewg<DIM>());
   if (mode == 0) hipLaunchKernelGGL((k_kin_stage<DIM, 0>), g, b, 0, s, A, io);
   else if (mode == 1) hipLaunchKernelGGL((k_kin_stage<DIM, 1>), g, b, 0, s, A, io);
   else hipLaunchKernelGGL((k_kin_stage<DIM, 2>), g, b, 0, s, A, io);
@@ -513,7 +518,7 @@ void kin_stage(const dg2p_mesh_s* m, int mode, const KArgs& A, const KinIO& io, 
 template <int DIM>
 void reinit_stage_d(int mode, const KArgs& A, const ReinitIO& io, hipStream_t s) {
   TimedLaunch t(DG2P_K_KIN_STAGE, s);
-  const dim3 g = elem_grid(A), b(BLOCK);
+  const dim3 g = elem_grid(A), b(ewg<DIM>());
   if (mode == 1) hipLaunchKernelGGL((k_reinit_stage<DIM, 1>), g, b, 0, s, A, io);
   else hipLaunchKernelGGL((k_reinit_stage<DIM, 2>), g, b, 0, s, A, io);
 }
@@ -824,7 +829,9 @@ int advance_impl(const dg2p_mesh_s* m, const dg2p_params* p, double* U, int n_st
   // records (rate-only or full) of the ingredient pass and of every step's
   // last stage, one per workgroup
   const long long nrec = elem_blocks(m);
-  const bool fused = !mon_steps && nrec <= FUSED_DT_MAX;
+  // a first-stage workgroup reduces up to FUSED_RATE_PER_THREAD records per thread
+  const long long fused_max = std::min<long long>(FUSED_DT_MAX, (long long)FUSED_RATE_PER_THREAD * elem_threads(m->dim));
+  const bool fused = !mon_steps && nrec <= fused_max;
   A.cfl = cfl;
   A.hmin = min_h(m);
   A.nrate = nrec;
@@ -1105,11 +1112,11 @@ int dg2p_kin_reinit(dg2p_mesh m, const dg2p_kin_params* kp, double* Phi, int n_i
   {
     TimedLaunch t(DG2P_K_INGREDIENTS, s);
     if (m->dim == 1)
-      hipLaunchKernelGGL(k_reinit_start<1>, elem_grid(A), dim3(BLOCK), 0, s, A, Phi, kp->eps, psi, sgn, G0);
+      hipLaunchKernelGGL(k_reinit_start<1>, elem_grid(A), dim3(ewg<1>()), 0, s, A, Phi, kp->eps, psi, sgn, G0);
     else if (m->dim == 2)
-      hipLaunchKernelGGL(k_reinit_start<2>, elem_grid(A), dim3(BLOCK), 0, s, A, Phi, kp->eps, psi, sgn, G0);
+      hipLaunchKernelGGL(k_reinit_start<2>, elem_grid(A), dim3(ewg<2>()), 0, s, A, Phi, kp->eps, psi, sgn, G0);
     else
-      hipLaunchKernelGGL(k_reinit_start<3>, elem_grid(A), dim3(BLOCK), 0, s, A, Phi, kp->eps, psi, sgn, G0);
+      hipLaunchKernelGGL(k_reinit_start<3>, elem_grid(A), dim3(ewg<3>()), 0, s, A, Phi, kp->eps, psi, sgn, G0);
   }
   for (int it = 0; it < n_iter; ++it) {
     ReinitIO io{};
@@ -1184,11 +1191,11 @@ int dg2p_kin_max_dt(dg2p_mesh m, const dg2p_kin_params* kp, const double* u0, do
       else if (m->dim == 2) hipLaunchKernelGGL(k_kin1_rate<2>, g, dim3(BLOCK), 0, s, n, u0, w.rec);
       else hipLaunchKernelGGL(k_kin1_rate<3>, g, dim3(BLOCK), 0, s, n, u0, w.rec);
     } else if (m->dim == 1) {
-      hipLaunchKernelGGL(k_kin_rate<1>, elem_grid(A), dim3(BLOCK), 0, s, A, u0, w.rec);
+      hipLaunchKernelGGL(k_kin_rate<1>, elem_grid(A), dim3(ewg<1>()), 0, s, A, u0, w.rec);
     } else if (m->dim == 2) {
-      hipLaunchKernelGGL(k_kin_rate<2>, elem_grid(A), dim3(BLOCK), 0, s, A, u0, w.rec);
+      hipLaunchKernelGGL(k_kin_rate<2>, elem_grid(A), dim3(ewg<2>()), 0, s, A, u0, w.rec);
     } else {
-      hipLaunchKernelGGL(k_kin_rate<3>, elem_grid(A), dim3(BLOCK), 0, s, A, u0, w.rec);
+      hipLaunchKernelGGL(k_kin_rate<3>, elem_grid(A), dim3(ewg<3>()), 0, s, A, u0, w.rec);
     }
   }
   finalize_rate(m, A, w, nrec, cfl, nullptr, dt, nullptr, s);

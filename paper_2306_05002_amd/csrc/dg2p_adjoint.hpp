@@ -247,21 +247,22 @@ struct VjpIO {
   int accumulate;      // gather: Out += result (else Out = result)
 };
 
+template <int WT>
 __device__ __forceinline__ void block_sum(double v, double* rec, long long blk) {
-  __shared__ double sh[BLOCK / 64];
+  __shared__ double sh[WT / 64];
   v = wave_sum(v);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
     double x = sh[0];
 #pragma unroll
-    for (int i = 1; i < BLOCK / 64; ++i) x += sh[i];
+    for (int i = 1; i < WT / 64; ++i) x += sh[i];
     rec[blk] = x;
   }
 }
 
 template <int DIM, bool VISC, bool CSF>
-__global__ __launch_bounds__(BLOCK) void k_vjp_local(KArgs A, VjpIO io) {
+__global__ __launch_bounds__(ewg<DIM>()) void k_vjp_local(KArgs A, VjpIO io) {
   constexpr int NN = 1 << (2 * DIM);
   constexpr int EPW = 64 / NN;
   constexpr int NF = DIM + 5;
@@ -272,7 +273,7 @@ __global__ __launch_bounds__(BLOCK) void k_vjp_local(KArgs A, VjpIO io) {
   const long long blk = logical_block(A);
   if (blk < 0) return;
   const int lane = threadIdx.x & 63;
-  const long long e0 = (blk * (BLOCK / 64) + (threadIdx.x >> 6)) * EPW + lane / NN;
+  const long long e0 = (blk * (ewg<DIM>() / 64) + (threadIdx.x >> 6)) * EPW + lane / NN;
   const bool valid = e0 < A.E;
   const long long e = valid ? e0 : A.E - 1;
   const int node = lane % NN;
@@ -568,11 +569,11 @@ __global__ __launch_bounds__(BLOCK) void k_vjp_local(KArgs A, VjpIO io) {
 #pragma unroll
     for (int f = 0; f < NF; ++f) io.T[f * fs + o] = qb[f];
   }
-  if constexpr (CSF) block_sum(sigb, io.rec, blk);
+  if constexpr (CSF) block_sum<ewg<DIM>()>(sigb, io.rec, blk);
 }
 
 template <int DIM, bool VISC>
-__global__ __launch_bounds__(BLOCK) void k_vjp_gather(KArgs A, VjpIO io) {
+__global__ __launch_bounds__(ewg<DIM>()) void k_vjp_gather(KArgs A, VjpIO io) {
   constexpr int NN = 1 << (2 * DIM);
   constexpr int EPW = 64 / NN;
   constexpr int NF = DIM + 5;
@@ -582,7 +583,7 @@ __global__ __launch_bounds__(BLOCK) void k_vjp_gather(KArgs A, VjpIO io) {
   const long long blk = logical_block(A);
   if (blk < 0) return;
   const int lane = threadIdx.x & 63;
-  const long long e0 = (blk * (BLOCK / 64) + (threadIdx.x >> 6)) * EPW + lane / NN;
+  const long long e0 = (blk * (ewg<DIM>() / 64) + (threadIdx.x >> 6)) * EPW + lane / NN;
   const bool valid = e0 < A.E;
   const long long e = valid ? e0 : A.E - 1;
   const int node = lane % NN;

@@ -38,6 +38,15 @@
 namespace dg2p {
 
 constexpr int BLOCK = 256;      // threads per workgroup (4 independent waves)
+// Threads per workgroup of the element passes: hexahedra run one wave (one
+// element) per workgroup, so that a finished wave's slot takes new work at
+// once instead of waiting for the other waves of a four-wave workgroup; the
+// other dimensions keep four waves (their small grids reduce the time step
+// inside the first stage, which needs the records of few workgroups).
+template <int DIM>
+constexpr int ewg() {
+  return DIM == 3 ? 64 : BLOCK;
+}
 // minimum resident waves per SIMD the register allocator targets, per dimension
 #ifndef DG2P_WAVES_1D
 #define DG2P_WAVES_1D 4
@@ -618,8 +627,9 @@ __device__ __forceinline__ double wave_sum(double v) { return wave_all<0>(v); }
 // Rate record of a workgroup (2 doubles: largest wave speed and largest
 // kinematic viscosity): wave max, then the workgroup's 4 waves.
 constexpr int RATE = 2;
+template <int WT = BLOCK>
 __device__ __forceinline__ void block_rate_record(double w, double nu, double* rec, long long blk) {
-  __shared__ double sh[2][BLOCK / 64];
+  __shared__ double sh[2][WT / 64];
   w = wave_max(w);
   nu = wave_max(nu);
   if ((threadIdx.x & 63) == 0) {
@@ -631,7 +641,7 @@ __device__ __forceinline__ void block_rate_record(double w, double nu, double* r
     const int s = threadIdx.x;  // R_WAVE, R_NU
     double x = sh[s][0];
 #pragma unroll
-    for (int i = 1; i < BLOCK / 64; ++i) x = nan_max(x, sh[s][i]);
+    for (int i = 1; i < WT / 64; ++i) x = nan_max(x, sh[s][i]);
     rec[blk * RATE + s] = x;
   }
 }
@@ -650,15 +660,16 @@ __device__ __forceinline__ double rate_of(double wmax, double numax, double Gamm
 // overlap those of the stage input: each thread's maximum over its share of
 // the records (independent loads), then its wave's maximum, parked in LDS.
 constexpr int FUSED_RATE_PER_THREAD = 4;
-constexpr long long FUSED_RATE_MAX = FUSED_RATE_PER_THREAD * BLOCK;  // records one workgroup reduces
+constexpr long long FUSED_RATE_MAX = FUSED_RATE_PER_THREAD * BLOCK;  // records a four-wave workgroup reduces
+template <int WT>
 __device__ __forceinline__ void fused_dt_load(const KArgs& A, const double* __restrict__ rate,
-                                              double (*sh)[BLOCK / 64]) {
+                                              double (*sh)[WT / 64]) {
   // A.nrate <= FUSED_RATE_MAX: straight-line loads (clamped to record 0,
   // their values discarded), no loop whose latch would wait for every load
   double vw[FUSED_RATE_PER_THREAD], vn[FUSED_RATE_PER_THREAD];
 #pragma unroll
   for (int u = 0; u < FUSED_RATE_PER_THREAD; ++u) {
-    const long long r = threadIdx.x + u * BLOCK;
+    const long long r = threadIdx.x + u * WT;
     const long long rr = r < A.nrate ? r : 0;
     vw[u] = rate[rr * RATE + R_WAVE];
     vn[u] = rate[rr * RATE + R_NU];
@@ -666,7 +677,7 @@ __device__ __forceinline__ void fused_dt_load(const KArgs& A, const double* __re
   double w = 0.0, nu = 0.0;
 #pragma unroll
   for (int u = 0; u < FUSED_RATE_PER_THREAD; ++u) {
-    const bool ok = threadIdx.x + u * BLOCK < A.nrate;
+    const bool ok = threadIdx.x + u * WT < A.nrate;
     w = nan_max(w, ok ? vw[u] : 0.0);
     nu = nan_max(nu, ok ? vn[u] : 0.0);
   }
@@ -681,12 +692,13 @@ __device__ __forceinline__ void fused_dt_load(const KArgs& A, const double* __re
 // Second half, at the stage combine (the first point that needs dt, so that
 // the workgroup barrier does not hold the waves back at entry): the maxima
 // over the workgroup's waves, and dt from them.
-__device__ __forceinline__ double fused_dt_finish(const KArgs& A, double (*sh)[BLOCK / 64], int dim) {
+template <int WT>
+__device__ __forceinline__ double fused_dt_finish(const KArgs& A, double (*sh)[WT / 64], int dim) {
   __syncthreads();
   double w = sh[0][0];
   double nu = sh[1][0];
 #pragma unroll
-  for (int i = 1; i < BLOCK / 64; ++i) {
+  for (int i = 1; i < WT / 64; ++i) {
     w = nan_max(w, sh[0][i]);
     nu = nan_max(nu, sh[1][i]);
   }
@@ -786,8 +798,9 @@ __device__ __forceinline__ double wave_reduce_scatter(double* v) {
 }
 
 // Workgroup reduction of per-lane records into rec[blk * REC + slot] (fixed order).
+template <int WT = BLOCK>
 __device__ __forceinline__ void block_record(double* v, double* rec, long long blk) {
-  __shared__ double sh[REC][BLOCK / 64];
+  __shared__ double sh[REC][WT / 64];
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   // max group: wave, nu, -min alpha, max alpha, dev p, dev u (padded to 8)
@@ -817,7 +830,7 @@ __device__ __forceinline__ void block_record(double* v, double* rec, long long b
     const int s = threadIdx.x;
     double x = sh[s][0];
 #pragma unroll
-    for (int i = 1; i < BLOCK / 64; ++i) x = rec_combine(s, x, sh[s][i]);
+    for (int i = 1; i < WT / 64; ++i) x = rec_combine(s, x, sh[s][i]);
     rec[blk * REC + s] = x;
   }
 }
@@ -873,7 +886,7 @@ __device__ __forceinline__ void emit(const KArgs& A, const double* q, long long 
   if constexpr (REC_MODE == 2) {
     double v[REC];
     node_record<DIM, VISC>(A, q, p, node, valid, v);
-    block_record(v, rec, blk);
+    block_record<ewg<DIM>()>(v, rec, blk);
   } else if constexpr (REC_MODE == 1) {
     // time-step rate only: largest wave speed and kinematic viscosity
     double w = DIM * p.c;
@@ -884,14 +897,14 @@ __device__ __forceinline__ void emit(const KArgs& A, const double* q, long long 
       const double al = q[3 + DIM];
       nu = (A.mu1 * al + A.mu2 * (1.0 - al)) * rcp_nr(p.rho);
     }
-    block_rate_record(valid ? w : 0.0, valid ? nu : 0.0, rec, blk);
+    block_rate_record<ewg<DIM>()>(valid ? w : 0.0, valid ? nu : 0.0, rec, blk);
   }
 }
 
 // ---------------------------------------------------------------------------
 // Ingredient pass: G and records of a state (first stage of a step, residual).
 template <int DIM, bool VISC, int PR>
-__global__ __launch_bounds__(BLOCK) void k_ingredients(KArgs A, const double* __restrict__ U,
+__global__ __launch_bounds__(ewg<DIM>()) void k_ingredients(KArgs A, const double* __restrict__ U,
                                                        double* __restrict__ G, double* __restrict__ rec) {
   constexpr int NN = 1 << (2 * DIM);
   constexpr int EPW = 64 / NN;
@@ -899,7 +912,7 @@ __global__ __launch_bounds__(BLOCK) void k_ingredients(KArgs A, const double* __
   const long long blk = logical_block(A);
   if (blk < 0) return;
   const int lane = threadIdx.x & 63;
-  const long long e0 = (blk * (BLOCK / 64) + (threadIdx.x >> 6)) * EPW + lane / NN;
+  const long long e0 = (blk * (ewg<DIM>() / 64) + (threadIdx.x >> 6)) * EPW + lane / NN;
   const bool valid = e0 < A.E;
   const long long e = valid ? e0 : A.E - 1;
   const int node = lane % NN;
@@ -1176,7 +1189,7 @@ __device__ __forceinline__ void spread_sym(const KArgs& A, int akk, const double
 // periodic mesh (no ghost code), 1 = walls / extrapolation, 2 = also kinds
 // that read the side's bc_state (Dirichlet, Riemann).
 template <int DIM, bool VISC, bool CSF, int BCK, int MODE, int EPI, int PR>
-__global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs A, StageIO io) {
+__global__ __launch_bounds__(ewg<DIM>(), (min_waves<DIM, VISC>())) void k_stage(KArgs A, StageIO io) {
   constexpr int NN = 1 << (2 * DIM);
   constexpr int EPW = 64 / NN;
   constexpr int NF = DIM + 5;
@@ -1188,7 +1201,8 @@ __global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs
   // readfirstlane so that for hexahedra (one element per wave) the element,
   // its grid coordinates, neighbours and boundary tests are scalar values
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const long long e0 = (blk * (BLOCK / 64) + wv) * EPW + lane / NN;
+  constexpr int WT = ewg<DIM>();
+  const long long e0 = (blk * (WT / 64) + wv) * EPW + lane / NN;
   const bool valid = e0 < A.E;
   const long long e = valid ? e0 : A.E - 1;
   const int node = lane % NN;
@@ -1209,9 +1223,9 @@ __global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs
     if (!(MODE == 1 && io.dt_out)) dt_in = *io.dt;
   }
   // first stage of a small grid: the rate records of the time step
-  __shared__ double dt_lds[2][BLOCK / 64];
+  __shared__ double dt_lds[2][WT / 64];
   if constexpr (MODE == 1) {
-    if (io.dt_out && !io.dt_fixed) fused_dt_load(A, io.rate_in, dt_lds);
+    if (io.dt_out && !io.dt_fixed) fused_dt_load<WT>(A, io.rate_in, dt_lds);
   }
   // element multi-index and face neighbours
   long long ec[3] = {0, 0, 0};
@@ -1291,8 +1305,8 @@ __global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs
   //   slice un[w][f][node].
   constexpr bool Z_LDS = DIM == 3;
   constexpr bool UN_LDS = DIM == 3 && MODE == 2;
-  __shared__ __attribute__((aligned(16))) double zt_lds[Z_LDS ? BLOCK / 64 : 1][Z_LDS ? 3 : 1][Z_LDS ? 128 : 1];
-  __shared__ __attribute__((aligned(16))) double un_lds[UN_LDS ? BLOCK / 64 : 1][UN_LDS ? NF : 1][UN_LDS ? NN : 1];
+  __shared__ __attribute__((aligned(16))) double zt_lds[Z_LDS ? WT / 64 : 1][Z_LDS ? 3 : 1][Z_LDS ? 128 : 1];
+  __shared__ __attribute__((aligned(16))) double un_lds[UN_LDS ? WT / 64 : 1][UN_LDS ? NF : 1][UN_LDS ? NN : 1];
   if constexpr (Z_LDS) {
     constexpr int C = VISC ? 1 + DIM : 1;
     const int w = threadIdx.x >> 6;
@@ -1528,7 +1542,7 @@ __global__ __launch_bounds__(BLOCK, (min_waves<DIM, VISC>())) void k_stage(KArgs
   double dt_fused = 0.0;
   if constexpr (MODE == 1) {
     if (io.dt_out) {
-      dt_fused = io.dt_fixed ? *io.dt_fixed : fused_dt_finish(A, dt_lds, DIM);
+      dt_fused = io.dt_fixed ? *io.dt_fixed : fused_dt_finish<WT>(A, dt_lds, DIM);
       if (blk == 0 && threadIdx.x == 0) {
         *io.dt_out = dt_fused;
         if (io.t) *io.t += dt_fused;

@@ -68,14 +68,14 @@ __device__ __forceinline__ void kin_emit(const KArgs& A, double phi, double psi,
 }
 
 template <int DIM>
-__global__ __launch_bounds__(BLOCK) void k_kin_ingredients(KArgs A, const double* __restrict__ P,
+__global__ __launch_bounds__(ewg<DIM>()) void k_kin_ingredients(KArgs A, const double* __restrict__ P,
                                                            double* __restrict__ G) {
   constexpr int NN = 1 << (2 * DIM);
   constexpr int EPW = 64 / NN;
   const long long blk = logical_block(A);
   if (blk < 0) return;
   const int lane = threadIdx.x & 63;
-  const long long e0 = (blk * (BLOCK / 64) + (threadIdx.x >> 6)) * EPW + lane / NN;
+  const long long e0 = (blk * (ewg<DIM>() / 64) + (threadIdx.x >> 6)) * EPW + lane / NN;
   const bool valid = e0 < A.E;
   const long long e = valid ? e0 : A.E - 1;
   const int node = lane % NN;
@@ -92,14 +92,14 @@ __global__ __launch_bounds__(BLOCK) void k_kin_ingredients(KArgs A, const double
 // MODE 0: Out = R.  MODE 1: Acc = (first ? 0 : Acc) + wacc R, Out = Pn + cdt R,
 // and Gout for Out.  MODE 2: Out = Pn + dt6 (Acc + R) and Gout for Out.
 template <int DIM, int MODE>
-__global__ __launch_bounds__(BLOCK) void k_kin_stage(KArgs A, KinIO io) {
+__global__ __launch_bounds__(ewg<DIM>()) void k_kin_stage(KArgs A, KinIO io) {
   constexpr int NN = 1 << (2 * DIM);
   constexpr int EPW = 64 / NN;
   constexpr int NFN = NN / 4;
   const long long blk = logical_block(A);
   if (blk < 0) return;
   const int lane = threadIdx.x & 63;
-  const long long e0 = (blk * (BLOCK / 64) + (threadIdx.x >> 6)) * EPW + lane / NN;
+  const long long e0 = (blk * (ewg<DIM>() / 64) + (threadIdx.x >> 6)) * EPW + lane / NN;
   const bool valid = e0 < A.E;
   const long long e = valid ? e0 : A.E - 1;
   const int node = lane % NN;
@@ -215,14 +215,14 @@ __global__ __launch_bounds__(BLOCK) void k_kin_stage(KArgs A, KinIO io) {
 // (the time factor is at most 1); the diffusive part Gamma eps enters through
 // the rate rule's nu_max = max(Gamma eps, 0).
 template <int DIM>
-__global__ __launch_bounds__(BLOCK) void k_kin_rate(KArgs A, const double* __restrict__ u0,
+__global__ __launch_bounds__(ewg<DIM>()) void k_kin_rate(KArgs A, const double* __restrict__ u0,
                                                     double* __restrict__ rec) {
   constexpr int NN = 1 << (2 * DIM);
   constexpr int EPW = 64 / NN;
   const long long blk = logical_block(A);
   if (blk < 0) return;
   const int lane = threadIdx.x & 63;
-  const long long e0 = (blk * (BLOCK / 64) + (threadIdx.x >> 6)) * EPW + lane / NN;
+  const long long e0 = (blk * (ewg<DIM>() / 64) + (threadIdx.x >> 6)) * EPW + lane / NN;
   const bool valid = e0 < A.E;
   const long long e = valid ? e0 : A.E - 1;
   const long long fs = A.E * NN;
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(BLOCK) void k_kin_rate(KArgs A, const double* __res
   double w = 0.0;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) w += fabs(u0[k * fs + o]);
-  block_rate_record(valid ? w : 0.0, 0.0, rec, blk);
+  block_rate_record<ewg<DIM>()>(valid ? w : 0.0, 0.0, rec, blk);
 }
 
 // Per-workgroup sums of W |phi - phi0|, W (phi - phi0), W phi0 (GLL
@@ -328,7 +328,7 @@ __device__ __forceinline__ void reinit_emit(const KArgs& A, double psi, long lon
 
 // psi0 = phi - 1/2 -> psi, smeared sign -> sgn, face ingredients of psi0 -> G.
 template <int DIM>
-__global__ __launch_bounds__(BLOCK) void k_reinit_start(KArgs A, const double* __restrict__ phi, double eps_phase,
+__global__ __launch_bounds__(ewg<DIM>()) void k_reinit_start(KArgs A, const double* __restrict__ phi, double eps_phase,
                                                         double* __restrict__ psi, double* __restrict__ sgn,
                                                         double* __restrict__ G) {
   constexpr int NN = 1 << (2 * DIM);
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(BLOCK) void k_reinit_start(KArgs A, const double* _
   const long long blk = logical_block(A);
   if (blk < 0) return;
   const int lane = threadIdx.x & 63;
-  const long long e0 = (blk * (BLOCK / 64) + (threadIdx.x >> 6)) * EPW + lane / NN;
+  const long long e0 = (blk * (ewg<DIM>() / 64) + (threadIdx.x >> 6)) * EPW + lane / NN;
   const bool valid = e0 < A.E;
   const long long e = valid ? e0 : A.E - 1;
   const int node = lane % NN;
@@ -364,14 +364,14 @@ __global__ __launch_bounds__(BLOCK) void k_reinit_start(KArgs A, const double* _
 // MODE 1: Acc = (first ? 0 : Acc) + wacc R, Out = Pn + cdt R (+ Gout);
 // MODE 2: Out = Pn + dt6 (Acc + R) (+ Gout).
 template <int DIM, int MODE>
-__global__ __launch_bounds__(BLOCK) void k_reinit_stage(KArgs A, ReinitIO io) {
+__global__ __launch_bounds__(ewg<DIM>()) void k_reinit_stage(KArgs A, ReinitIO io) {
   constexpr int NN = 1 << (2 * DIM);
   constexpr int EPW = 64 / NN;
   constexpr int NFN = NN / 4;
   const long long blk = logical_block(A);
   if (blk < 0) return;
   const int lane = threadIdx.x & 63;
-  const long long e0 = (blk * (BLOCK / 64) + (threadIdx.x >> 6)) * EPW + lane / NN;
+  const long long e0 = (blk * (ewg<DIM>() / 64) + (threadIdx.x >> 6)) * EPW + lane / NN;
   const bool valid = e0 < A.E;
   const long long e = valid ? e0 : A.E - 1;
   const int node = lane % NN;

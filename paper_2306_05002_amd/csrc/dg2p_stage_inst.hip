@@ -16,7 +16,7 @@ namespace {
 
 template <int DIM, bool VISC, bool CSF, int BCK, int PR>
 void stage_mode(int mode, int epi, const KArgs& A, const StageIO& io, hipStream_t s) {
-  const dim3 g((unsigned)(8 * A.xcd_chunk)), b(BLOCK);
+  const dim3 g((unsigned)(8 * A.xcd_chunk)), b(ewg<DIM>());
   if (mode == 0)
     hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, BCK, 0, 0, PR>), g, b, 0, s, A, io);
   else if (mode == 1)
@@ -51,7 +51,7 @@ void launch_stage_dp(int bck, bool visc, bool csf, int mode, int epi, const KArg
 
 template <int DIM, int PR>
 void launch_ingredients_dp(bool visc, const KArgs& A, const double* U, double* G, double* rec, hipStream_t s) {
-  const dim3 g((unsigned)(8 * A.xcd_chunk)), b(BLOCK);
+  const dim3 g((unsigned)(8 * A.xcd_chunk)), b(ewg<DIM>());
   if (visc) hipLaunchKernelGGL((k_ingredients<DIM, true, PR>), g, b, 0, s, A, U, G, rec);
   else hipLaunchKernelGGL((k_ingredients<DIM, false, PR>), g, b, 0, s, A, U, G, rec);
 }

@@ -14,7 +14,7 @@ namespace {
 
 template <int DIM, bool VISC, bool CSF>
 void vjp_passes(const KArgs& A, const VjpIO& io, hipStream_t s) {
-  const dim3 g((unsigned)(8 * A.xcd_chunk)), b(BLOCK);
+  const dim3 g((unsigned)(8 * A.xcd_chunk)), b(ewg<DIM>());
   hipLaunchKernelGGL((k_vjp_local<DIM, VISC, CSF>), g, b, 0, s, A, io);
   hipLaunchKernelGGL((k_vjp_gather<DIM, VISC>), g, b, 0, s, A, io);
 }
