@@ -183,9 +183,22 @@ def kinematic_section():
                 row.update(l1_reinit=r1["l1"], mass_error_reinit=r1["mass_error"], reinit_calls=r1["reinit"])
             row.update(ms_per_step=r0["ms"] / r0["steps"], value=4.0 * r0["dof"] * r0["steps"] / (r0["ms"] * 1e-3))
             rows.append(row)
+    adv = {}
+    for psi, eps in (("cone", 0.05), ("smooth", 0.025)):
+        for order, Ns in ((3, (8, 16, 32, 64)), (1, (16, 32, 64, 128))):
+            errs = [kinematic.advected_droplet(N, order=order, psi=psi, eps=eps) for N in Ns]
+            l1 = [r["l1"] for r in errs]
+            adv[f"p{order}_{psi}_psi_eps{eps}"] = {
+                "elements": list(Ns), "l1": l1, "mass_error": [r["mass_error"] for r in errs],
+                "order": [math.log2(l1[i] / l1[i + 1]) for i in range(len(l1) - 1)]}
     return {"workload": "rk2d: Rider-Kothe vortex, [0,1]^2 periodic, p=3 and p=1, eps=2h/(p+1), Gamma=1, T=4, "
                         "RK4, CFL 0.1",
-            "unit": "DOF-updates/s", "runs": rows}
+            "unit": "DOF-updates/s", "runs": rows,
+            "linear_advection": {"workload": "adv2d: droplet R=0.15 carried by u=(1,0) for one period, [0,1]^2 "
+                                             "periodic, Gamma=1, RK4, CFL 0.1; the paper's set-up (level set "
+                                             "psi = R - r, eps = 0.05 fixed) and a smooth level set "
+                                             "(R^2 - r^2)/(2R) with eps = 0.025",
+                                 "runs": adv}}
 
 
 def waterair_section():

@@ -4,8 +4,9 @@ set under a prescribed velocity; Results, "Kinematic tests").
 ``rider_kothe`` runs the single-vortex case for one period with classical
 RK4 at the kinematic time-step rule and, optionally, the level-set
 re-initialisation of the paper's runs (50 pseudo-time iterations every 2000
-physical steps).  Every step runs in the library's kernels; this module only
-sequences the calls.
+physical steps); ``advected_droplet`` runs the linear advection of a droplet
+for one period (the convergence study of the same section).  Every step runs
+in the library's kernels; this module only sequences the calls.
 """
 
 import math
@@ -17,13 +18,28 @@ from . import dg2p, workloads
 
 
 def rider_kothe(N, reinit_every=0, reinit_iters=50, time_it=False, order=3, velocity="nodal"):
-    """One Rider-Kothe period on N x N elements of degree `order` (3 or 1; the
-    re-initialisation is p = 3 only).  velocity "nodal": the analytic field
+    """One Rider-Kothe period on N x N elements (see ``run``)."""
+    return run("rk2d", N, reinit_every, reinit_iters, time_it, order, velocity)
+
+
+def advected_droplet(N, order=3, time_it=False, psi="cone", eps=None):
+    """One period of the droplet carried by u = (1, 0) on N x N elements
+    (fixed eps = 0.05 unless given, Gamma = 1; level set `psi` as in
+    workloads.kinematic_config): the L1 error against the initial field and
+    the relative mass error."""
+    return run("adv2d", N, 0, 0, time_it, order, "nodal", psi, eps)
+
+
+def run(name, N, reinit_every=0, reinit_iters=50, time_it=False, order=3, velocity="nodal", psi="cone",
+        eps=None):
+    """One period of the kinematic case `name` (workloads.KIN_NAMES) on N x N
+    elements of degree `order` (3 or 1; the re-initialisation, every
+    `reinit_every` steps, is p = 3 only).  velocity "nodal": the analytic field
     at the nodes; "stream": the field from the nodal stream function
     (dg2p_kin_velocity_from_stream, discretely divergence free).  Returns a
     dict with the L1 error, the relative mass error, the step count and
     (time_it) the elapsed milliseconds of the whole run."""
-    cfg = workloads.kinematic_config("rk2d", n_elem=(N, N), order=order)
+    cfg = workloads.kinematic_config(name, n_elem=(N, N), order=order, psi=psi, eps=eps)
     mesh = dg2p.Mesh(2, (N, N), cfg["lo"], cfg["hi"], order=order)
     phi, psi, u0 = workloads.kinematic_fields(cfg, mesh.node_coords())
     kp = dg2p.make_kin_params(**cfg["kin"])

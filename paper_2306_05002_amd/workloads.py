@@ -325,7 +325,7 @@ KIN_NAMES = ("rk2d", "adv2d")
 KIN_FULL_ELEMS = {"rk2d": (16, 16), "adv2d": (16, 16)}
 
 
-def kinematic_config(name, n_elem=None, order=ORDER):
+def kinematic_config(name, n_elem=None, order=ORDER, psi="cone", eps=None):
     """Kinematic test cases of the Results section, p = 3 (or 1) on [0,1]^2,
     periodic.
 
@@ -335,19 +335,29 @@ def kinematic_config(name, n_elem=None, order=ORDER):
            spacings (h / 2 at p = 3, the element size h at p = 1)
     adv2d  linear advection of a droplet R = 0.15 at (0.5, 0.5) by u = (1, 0)
            for one period, fixed eps = 0.05, Gamma = 1
+
+    psi "cone": the level set is the signed distance R - r (the paper's
+    choice; its gradient has a cone tip at the centre); "smooth": (R^2 - r^2)
+    / (2R), the same zero level and the same normal direction away from the
+    centre, polynomial (so its nodal gradient is exact for p >= 2).  eps
+    overrides the interface thickness.
     """
     if name not in KIN_NAMES:
         raise KeyError(name)
     n_elem = tuple(n_elem) if n_elem is not None else KIN_FULL_ELEMS[name]
     h = 1.0 / n_elem[0]
+    if psi not in ("cone", "smooth"):
+        raise ValueError("psi must be 'cone' or 'smooth'")
     cfg = dict(name=name, dim=2, order=order, n_elem=n_elem, lo=(0.0, 0.0), hi=(1.0, 1.0),
-               bc=[("periodic", "periodic")] * 2, cfl=0.1)
+               bc=[("periodic", "periodic")] * 2, cfl=0.1, psi=psi)
     if name == "rk2d":
         cfg.update(kin=dict(Gamma=1.0, eps=2.0 * h / (order + 1), c_ip=1.0, grad_reg=1e-12, period=4.0),
                    t_end=4.0, centre=(0.5, 0.75))
     else:
         cfg.update(kin=dict(Gamma=1.0, eps=0.05, c_ip=1.0, grad_reg=1e-12, period=0.0),
                    t_end=1.0, centre=(0.5, 0.5))
+    if eps is not None:
+        cfg["kin"]["eps"] = float(eps)
     return cfg
 
 
@@ -357,8 +367,9 @@ def kinematic_fields(cfg, X):
     x, y = X[0], X[1]
     cx, cy = cfg["centre"]
     eps = cfg["kin"]["eps"]
-    psi = 0.15 - np.sqrt((x - cx) ** 2 + (y - cy) ** 2)
-    phi = _sigmoid(psi / eps)
+    r = np.sqrt((x - cx) ** 2 + (y - cy) ** 2)
+    phi = _sigmoid((0.15 - r) / eps)
+    psi = 0.15 - r if cfg.get("psi", "cone") == "cone" else (0.15 ** 2 - r ** 2) / (2 * 0.15)
     if cfg["name"] == "rk2d":
         u0 = np.stack([np.sin(math.pi * x) ** 2 * np.sin(2 * math.pi * y),
                        -np.sin(2 * math.pi * x) * np.sin(math.pi * y) ** 2])
