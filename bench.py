@@ -301,7 +301,8 @@ def walls_section():
             else:
                 light = a > 0.5
                 rows.append({"t_star": tn / t_scale, "top": float(y[light].max()),
-                             "bottom": float(y[~light].min()), "nonphys": m["nonphys"]})
+                             "bottom": float(y[~light].min()), "nonphys": m["nonphys"],
+                             "min_partial_density": [float(U[0].min()), float(U[1].min())]})
         out[name] = {"workload": f"{name}: {WORKLOAD_DESC[name]}", "steps": steps, "series": rows,
                      "ms_per_step": ms / steps, "value": 3.0 * dof * steps / (ms * 1e-3),
                      "unit": "DOF-updates/s"}
