@@ -333,6 +333,30 @@ def field_errors(Ua, Ub, Wn, d, n_steps):
     return {"after_steps": n_steps, "l2_rel": [float(x) for x in l2], "linf_rel": [float(x) for x in linf]}
 
 
+def copy_bandwidth(gib=2.0, reps=10):
+    """Achieved HBM bandwidth of a plain device copy (torch's copy kernel,
+    `gib` GiB read and written per launch, well beyond the 256 MB Infinity
+    Cache): bytes moved / mean launch time, HIP events on the current
+    stream.  Context for the roofline fraction: what a streaming kernel with
+    no arithmetic reaches on this GPU."""
+    import torch
+    n = int(gib * (1 << 30) / 8)
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x, y
+    return 2.0 * n * 8 / (ms * 1e-3) / 1e9
+
+
 def calibrate_copy(gib=2.0, reps=10):
     """Plain copy kernel of known size (reads and writes `gib` GiB) for
     scaling the HBM counters of the profiler."""
@@ -583,6 +607,12 @@ def main():
     rl = roofline(args.workload, dof, stage_ms, k_ms["stage"][0], src)
     if args.workload not in HBM_RESIDENT:
         rl["bound"] = "infinity-cache resident (fabric, not HBM)"
+    else:
+        cbw = copy_bandwidth()
+        rl["copy_kernel_gbs"] = cbw
+        rl["frac_of_copy_kernel"] = rl["achieved"] / cbw
+        if rl["traffic"] is not None:
+            rl["traffic_gbs"] = rl["traffic"] / (rl["kernel_mean_ms"] * 1e-3) / 1e9
     last = mon_rows[-1]
     monitors = {"per_step": True, "steps_with_nonphys": sum(1 for r in mon_rows if r["nonphys"]),
                 "last_step": {"nonphys": last["nonphys"], "min_alpha": last["min_alpha"],

@@ -3,7 +3,8 @@
 The library is linked from several objects compiled in parallel: the host
 entry points (dg2p.hip), the stage and ingredient kernels once per
 (dimension, contraction precision) pair (dg2p_stage_inst.hip with
--DDG2P_DIM / -DDG2P_PR) and the residual VJP kernels once per dimension
+-DDG2P_DIM / -DDG2P_PR), the kernels of quadrilaterals of degree 4
+(dg2p_stage_gen.hip) and the residual VJP kernels once per dimension
 (dg2p_vjp_inst.hip).
 """
 
@@ -30,7 +31,7 @@ NOISE = "is not a recognized feature for this target"
 
 def units():
     """(object name, source, extra defines) of every translation unit."""
-    u = [("dg2p_host", "dg2p.hip", [])]
+    u = [("dg2p_host", "dg2p.hip", []), ("stage_gen", "dg2p_stage_gen.hip", [])]
     for d in (1, 2, 3):
         for p in (0, 1, 2):
             u.append((f"stage_d{d}_p{p}", "dg2p_stage_inst.hip", [f"-DDG2P_DIM={d}", f"-DDG2P_PR={p}"]))

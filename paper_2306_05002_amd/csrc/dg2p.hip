@@ -37,7 +37,7 @@ struct dg2p_mesh_s {
   long long E;
   int nn, nf, nfn;
   double h[3], J[3];
-  double xi[4], w[4], D[4][4];
+  double xi[8], w[8], D[8][8];
 };
 
 namespace {
@@ -54,14 +54,24 @@ int hip_check(hipError_t e, const char* what) {
   return fail(DG2P_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-// GLL nodes and weights of degree 3 (or 1) in closed form, and the Lagrange
+// GLL nodes and weights of degree 1, 3 or 4 in closed form, and the Lagrange
 // derivative matrix D[a][b] = l_b'(xi_a) from the product rule.
-void gll(int p, double* x, double* w, double (*D)[4]) {
+void gll(int p, double* x, double* w, double (*D)[8]) {
   const int n = p + 1;
   if (p == 1) {
     x[0] = -1.0;
     x[1] = 1.0;
     w[0] = w[1] = 1.0;
+  } else if (p == 4) {
+    const double s = std::sqrt(3.0 / 7.0);
+    x[0] = -1.0;
+    x[1] = -s;
+    x[2] = 0.0;
+    x[3] = s;
+    x[4] = 1.0;
+    w[0] = w[4] = 1.0 / 10.0;
+    w[1] = w[3] = 49.0 / 90.0;
+    w[2] = 32.0 / 45.0;
   } else {
     const double s = 1.0 / std::sqrt(5.0);
     x[0] = -1.0;
@@ -92,8 +102,12 @@ void gll(int p, double* x, double* w, double (*D)[4]) {
 
 int check_params(const dg2p_mesh_s* m, const dg2p_params* p) {
   if (!p) return fail(DG2P_EINVAL, "params is NULL");
-  if (m && m->desc.order != 3)
-    return fail(DG2P_EUNSUPPORTED, "the two-phase model is implemented for p = 3 (p = 1: kinematic mode only)");
+  if (m && m->desc.order != 3) {
+    if (m->desc.order != 4 || m->dim != 2)
+      return fail(DG2P_EUNSUPPORTED,
+                  "the two-phase model is implemented for p = 3, and p = 4 on quadrilaterals (p = 1: kinematic mode only)");
+    if (p->precision != DG2P_FP64) return fail(DG2P_EUNSUPPORTED, "p = 4 runs in FP64 only");
+  }
   for (int l = 0; l < 2; ++l) {
     if (!(p->gamma[l] > 1.0)) return fail(DG2P_EINVAL, "gamma must be > 1");
     if (!std::isfinite(p->pinf[l]) || !std::isfinite(p->rho0[l]))
@@ -111,15 +125,21 @@ int check_params(const dg2p_mesh_s* m, const dg2p_params* p) {
 }
 
 
-// Threads per workgroup of the element passes of a mesh (ewg<DIM>()).
-int elem_threads(int dim) { return dim == 3 ? ewg<3>() : (dim == 2 ? ewg<2>() : ewg<1>()); }
+// Threads per workgroup of the element passes of a mesh (ewg<DIM>(); the
+// quadrilaterals of degree != 3 run one-wave workgroups of two elements).
+bool generic_order(const dg2p_mesh_s* m) { return m->desc.order != 3; }
+int elem_threads(const dg2p_mesh_s* m) {
+  if (generic_order(m) && m->dim == 2) return 64;
+  return m->dim == 3 ? ewg<3>() : (m->dim == 2 ? ewg<2>() : ewg<1>());
+}
+// Elements per wave of the element passes.
+int elems_per_wave(const dg2p_mesh_s* m) { return generic_order(m) ? 2 : (64 >> (2 * m->dim)); }
 
 KArgs make_args(const dg2p_mesh_s* m, const dg2p_params* p) {
   KArgs A;
   std::memset(&A, 0, sizeof(A));
   A.E = m->E;
-  const int epw = 64 >> (2 * m->dim);
-  const long long per_wg = (long long)(elem_threads(m->dim) / 64) * epw;  // elements per workgroup
+  const long long per_wg = (long long)(elem_threads(m) / 64) * elems_per_wave(m);  // elements per workgroup
   A.nblocks = (m->E + per_wg - 1) / per_wg;
   A.xcd_chunk = (A.nblocks + 7) / 8;
   for (int k = 0; k < 3; ++k) {
@@ -162,6 +182,10 @@ KArgs make_args(const dg2p_mesh_s* m, const dg2p_params* p) {
   A.delta = p->grad_reg;
   A.rk_a = 0.0;
   A.rk_b = 1.0;
+  for (int a = 0; a <= m->desc.order && a < 8; ++a) {
+    A.gw[a] = m->w[a];
+    for (int b = 0; b <= m->desc.order && b < 8; ++b) A.gD[a][b] = m->D[a][b];
+  }
   return A;
 }
 
@@ -218,7 +242,7 @@ size_t state_bytes(const dg2p_mesh_s* m) {
 constexpr long long REC2_MAX = 1024;   // second-level records
 constexpr long long REC_GRID = 1024;   // workgroups of the stand-alone record pass
 long long elem_blocks(const dg2p_mesh_s* m) {
-  const long long per = (long long)(elem_threads(m->dim) / 64) * (64 >> (2 * m->dim));
+  const long long per = (long long)(elem_threads(m) / 64) * elems_per_wave(m);
   return (m->E + per - 1) / per;
 }
 size_t rec_bytes(const dg2p_mesh_s* m) {
@@ -304,6 +328,10 @@ void launch_stage(const dg2p_mesh_s* m, const dg2p_params* p, int mode, int epi,
   TimedLaunch t(DG2P_K_STAGE, s);
   const bool visc = viscous(p), csf = p->sigma != 0.0;
   const int bck = bc_class(m);
+  if (generic_order(m)) {
+    launch_stage_gen(m->desc.order, bck, visc, csf, mode, epi, A, io, s);
+    return;
+  }
   if (p->precision == DG2P_MIXED_FP32) stage_dim<1>(m->dim, bck, visc, csf, mode, epi, A, io, s);
   else if (p->precision == DG2P_MIXED_BF16) stage_dim<2>(m->dim, bck, visc, csf, mode, epi, A, io, s);
   else stage_dim<0>(m->dim, bck, visc, csf, mode, epi, A, io, s);
@@ -320,6 +348,10 @@ void launch_ingr(const dg2p_mesh_s* m, const dg2p_params* p, const KArgs& A, con
                  double* rec, hipStream_t s) {
   TimedLaunch t(DG2P_K_INGREDIENTS, s);
   const bool v = viscous(p);
+  if (generic_order(m)) {
+    launch_ingredients_gen(m->desc.order, v, A, U, G, rec, s);
+    return;
+  }
   if (p->precision == DG2P_MIXED_FP32) ingr_dim<1>(m->dim, v, A, U, G, rec, s);
   else if (p->precision == DG2P_MIXED_BF16) ingr_dim<2>(m->dim, v, A, U, G, rec, s);
   else ingr_dim<0>(m->dim, v, A, U, G, rec, s);
@@ -333,6 +365,10 @@ void launch_records(const dg2p_mesh_s* m, const dg2p_params* p, const KArgs& A, 
   long long gb = (n + BLOCK - 1) / BLOCK;
   if (gb > REC_GRID) gb = REC_GRID;
   const dim3 g((unsigned)gb), b(BLOCK);
+  if (generic_order(m)) {
+    launch_records_gen(m->desc.order, v, (unsigned)gb, A, U, rec, s);
+    return;
+  }
   if (m->dim == 1) {
     if (v) hipLaunchKernelGGL((k_records<1, true>), g, b, 0, s, A, U, rec);
     else hipLaunchKernelGGL((k_records<1, false>), g, b, 0, s, A, U, rec);
@@ -374,7 +410,8 @@ void finalize(const dg2p_mesh_s* m, const KArgs& A, const Work& w, long long n, 
     src = w.rec2;
     n = nb;
   }
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, s, src, n, A.GammaEps, m->dim, m->nf, min_h(m),
+  const double pdim = (double)((m->desc.order + 1) * (m->desc.order + 1) * m->dim);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, s, src, n, A.GammaEps, pdim, m->nf, min_h(m),
                      cfl, dt_fixed, dt, t, mon);
 }
 
@@ -437,6 +474,7 @@ int check_kin(const dg2p_mesh_s* m, const dg2p_kin_params* kp) {
   if (!(kp->grad_reg >= 0.0)) return fail(DG2P_EINVAL, "grad_reg must be >= 0");
   if (!std::isfinite(kp->period)) return fail(DG2P_EINVAL, "period must be finite");
   if (!all_periodic(m)) return fail(DG2P_EUNSUPPORTED, "the kinematic mode supports periodic meshes only");
+  if (m->desc.order != 1 && m->desc.order != 3) return fail(DG2P_EUNSUPPORTED, "the kinematic mode runs p = 1 or 3");
   return DG2P_OK;
 }
 
@@ -598,8 +636,9 @@ int dg2p_create_mesh(const dg2p_mesh_desc* desc, dg2p_mesh* out) {
   if (!desc || !out) return fail(DG2P_EINVAL, "desc and out must be non-NULL");
   *out = nullptr;
   if (desc->dim < 1 || desc->dim > 3) return fail(DG2P_EINVAL, "dim must be 1, 2 or 3");
-  if (desc->order != 3 && desc->order != 1)
-    return fail(DG2P_EUNSUPPORTED, "polynomial order 3 (and 1 for the kinematic mode) is implemented");
+  if (desc->order != 3 && desc->order != 1 && !(desc->order == 4 && desc->dim == 2))
+    return fail(DG2P_EUNSUPPORTED,
+                "polynomial order 3, 4 on quadrilaterals, and 1 for the kinematic mode are implemented");
   long long E = 1;
   for (int k = 0; k < desc->dim; ++k) {
     if (desc->n_elem[k] < 1) return fail(DG2P_EINVAL, "n_elem must be >= 1");
@@ -830,8 +869,8 @@ int advance_impl(const dg2p_mesh_s* m, const dg2p_params* p, double* U, int n_st
   // last stage, one per workgroup
   const long long nrec = elem_blocks(m);
   // a first-stage workgroup reduces up to FUSED_RATE_PER_THREAD records per thread
-  const long long fused_max = std::min<long long>(FUSED_DT_MAX, (long long)FUSED_RATE_PER_THREAD * elem_threads(m->dim));
-  const bool fused = !mon_steps && nrec <= fused_max;
+  const long long fused_max = std::min<long long>(FUSED_DT_MAX, (long long)FUSED_RATE_PER_THREAD * elem_threads(m));
+  const bool fused = !mon_steps && nrec <= fused_max && !generic_order(m);
   A.cfl = cfl;
   A.hmin = min_h(m);
   A.nrate = nrec;
@@ -935,6 +974,7 @@ int dg2p_rhs_vjp(dg2p_mesh m, const dg2p_params* p, const double* U, const doubl
   if (st) return st;
   if (p->precision != DG2P_FP64) return fail(DG2P_EUNSUPPORTED, "the adjoint is FP64 only");
   if (!all_periodic(m)) return fail(DG2P_EUNSUPPORTED, "the adjoint supports periodic meshes only");
+  if (m->desc.order != 3) return fail(DG2P_EUNSUPPORTED, "the adjoint is implemented for p = 3");
   st = check_ws(work, work_bytes(m, p, DG2P_OP_RHS_VJP));
   if (st) return st;
   KArgs A = make_args(m, p);
@@ -963,6 +1003,7 @@ int dg2p_rk_step_vjp(dg2p_mesh m, const dg2p_params* p, const double* U_n, const
   if (st) return st;
   if (p->precision != DG2P_FP64) return fail(DG2P_EUNSUPPORTED, "the adjoint is FP64 only");
   if (!all_periodic(m)) return fail(DG2P_EUNSUPPORTED, "the adjoint supports periodic meshes only");
+  if (m->desc.order != 3) return fail(DG2P_EUNSUPPORTED, "the adjoint is implemented for p = 3");
   st = check_ws(work, work_bytes(m, p, DG2P_OP_RK_STEP_VJP));
   if (st) return st;
   KArgs A = make_args(m, p);
@@ -1151,6 +1192,8 @@ int dg2p_kin_velocity_from_stream(dg2p_mesh m, const double* S, double* u0, void
   if (!m || !S || !u0) return fail(DG2P_EINVAL, "mesh, S and u0 must be non-NULL");
   if (S == u0) return fail(DG2P_EINVAL, "u0 may not alias S");
   if (m->dim != 2) return fail(DG2P_EUNSUPPORTED, "the stream-function velocity is two-dimensional");
+  if (m->desc.order != 1 && m->desc.order != 3)
+    return fail(DG2P_EUNSUPPORTED, "the stream-function velocity is for the kinematic orders p = 1, 3");
   CurlArgs C{};
   const int n = m->desc.order + 1;
   for (int a = 0; a < n; ++a)

@@ -189,6 +189,10 @@ struct KArgs {
   // time-step rule of a fused step (dt reduced inside the first stage)
   double cfl, hmin;
   long long nrate;  // number of rate records
+  // quadrilaterals of degree != 3: the GLL weights and derivative matrix
+  // (D[i][b] = l_b'(xi_i)), built on the host
+  double gw[8];
+  double gD[8][8];
 };
 
 // Boundary kind of side `side` of axis k (both may vary between lanes).
@@ -705,10 +709,11 @@ __device__ __forceinline__ double fused_dt_finish(const KArgs& A, double (*sh)[W
   return A.cfl / rate_of(w, nu, A.GammaEps, 16.0 * dim, A.hmin);
 }
 
-// Per-node record contributions of a state (time-step rate and monitors).
+// Per-node record contributions of a state (time-step rate and monitors), W
+// the node's quadrature weight.
 template <int DIM, bool VISC>
-__device__ __forceinline__ void node_record(const KArgs& A, const double* q, const Prim& p, int node,
-                                            bool valid, double* v) {
+__device__ __forceinline__ void node_record_w(const KArgs& A, const double* q, const Prim& p, double W,
+                                              bool valid, double* v) {
   constexpr int NF = DIM + 5;
   double w = DIM * p.c;
 #pragma unroll
@@ -723,12 +728,6 @@ __device__ __forceinline__ void node_record(const KArgs& A, const double* q, con
   double du = 0.0;
 #pragma unroll
   for (int j = 0; j < DIM; ++j) du = nan_max(du, fabs(p.u[j] - A.u_ref[j]));
-  double W = 1.0;
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) {
-    const int a = (node >> (2 * k)) & 3;
-    W *= ((a == 0 || a == 3) ? GLL.w[0] : GLL.w[1]) * A.J[k];
-  }
   v[R_WAVE] = valid ? w : 0.0;
   v[R_NU] = valid ? nu : 0.0;
   v[R_AMIN] = valid ? al : INFINITY;
@@ -738,6 +737,19 @@ __device__ __forceinline__ void node_record(const KArgs& A, const double* q, con
   v[R_DEVU] = valid ? du : 0.0;
 #pragma unroll
   for (int f = 0; f < 8; ++f) v[R_INT + f] = (valid && f < NF) ? W * q[f] : 0.0;
+}
+
+// The same for a node of the p = 3 lane layout (node = sum_k a_k 4^k).
+template <int DIM, bool VISC>
+__device__ __forceinline__ void node_record(const KArgs& A, const double* q, const Prim& p, int node,
+                                            bool valid, double* v) {
+  double W = 1.0;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    const int a = (node >> (2 * k)) & 3;
+    W *= ((a == 0 || a == 3) ? GLL.w[0] : GLL.w[1]) * A.J[k];
+  }
+  node_record_w<DIM, VISC>(A, q, p, W, valid, v);
 }
 
 __device__ __forceinline__ double rec_combine(int slot, double a, double b) {
@@ -1735,14 +1747,14 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_records(const double* __restri
 // One workgroup of FIN_THREADS threads.
 constexpr int FIN_THREADS = 1024;
 static __global__ __attribute__((unused)) __launch_bounds__(FIN_THREADS) void k_finalize(const double* __restrict__ rec, long long n,
-                                                          double GammaEps, int dim, int nf, double hmin,
+                                                          double GammaEps, double pdim, int nf, double hmin,
                                                           double cfl, const double* dt_fixed, double* dt,
                                                           double* t, dg2p_monitors* mon) {
   __shared__ double red[REC];
   reduce_slots<REC, FIN_THREADS>(rec, 0, n, red);
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double rate = rate_of(red[R_WAVE], red[R_NU], GammaEps, 16.0 * dim, hmin);
+    const double rate = rate_of(red[R_WAVE], red[R_NU], GammaEps, pdim, hmin);
     const double d = dt_fixed ? *dt_fixed : cfl / rate;
     if (dt) *dt = d;
     if (t) *t += d;

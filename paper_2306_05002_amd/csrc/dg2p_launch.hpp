@@ -28,6 +28,15 @@ void launch_stage_dp(int bck, bool visc, bool csf, int mode, int epi, const KArg
 template <int DIM, int PR>
 void launch_ingredients_dp(bool visc, const KArgs& A, const double* U, double* G, double* rec, hipStream_t s);
 
+// Quadrilaterals of degree `order` != 3 (dg2p_stage_gen.hip): stage pass,
+// ingredient pass and standalone records (grid of `blocks` workgroups).
+void launch_stage_gen(int order, int bck, bool visc, bool csf, int mode, int epi, const KArgs& A,
+                      const StageIO& io, hipStream_t s);
+void launch_ingredients_gen(int order, bool visc, const KArgs& A, const double* U, double* G, double* rec,
+                            hipStream_t s);
+void launch_records_gen(int order, bool visc, unsigned blocks, const KArgs& A, const double* U, double* rec,
+                        hipStream_t s);
+
 // Residual VJP passes (k_vjp_local, k_vjp_gather) of dimension DIM.
 template <int DIM>
 void launch_vjp_dim(bool visc, bool csf, const KArgs& A, const VjpIO& io, hipStream_t s);

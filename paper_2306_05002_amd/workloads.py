@@ -77,17 +77,19 @@ def shock_states(pressure_ratio=10.0, gamma=1.4, rho_pre=1.0, p_pre=1.0):
     return rho_post, u_post, p_pre * pi_
 
 
-def config(name, n_elem=None):
+def config(name, n_elem=None, order=ORDER):
     """Mesh description and physical parameters of a configuration.
 
     ``n_elem`` overrides the element counts (reduced sizes for parity tests);
-    eps follows the rule eps = h / (2 (p+1)) of the configuration's own grid
-    (waterair2d, bubble2d, rt2d: eps = h / 2).
+    ``order`` the polynomial degree (3; 4 for the 2D configurations, the
+    degree of the paper's Rayleigh-Taylor and rising-bubble runs); eps follows
+    the rule eps = h / (2 (p+1)) of the configuration's own grid (waterair2d,
+    bubble2d, rt2d: eps = h / 2).
     """
     if name not in NAMES:
         raise KeyError(name)
     n_elem = tuple(n_elem) if n_elem is not None else FULL_ELEMS[name]
-    p = ORDER
+    p = int(order)
     base = dict(gamma=(1.4, 4.4), pinf=(0.0, 0.6), rho0=(1.0, 10.0), Gamma=1.0,
                 mu=(0.0, 0.0), sigma=0.0, g=(0.0, 0.0, 0.0), c_ip=1.0,
                 grad_reg=1e-12)

@@ -7,11 +7,12 @@ import oracle
 from paper_2306_05002_amd import workloads
 
 
-def oracle_setup(name, n_elem=None, variant=None, bc=None, bc_state=None, **param_over):
+def oracle_setup(name, n_elem=None, variant=None, bc=None, bc_state=None, order=3, **param_over):
     """(cfg, mesh, params, U0) for a configuration, built on the oracle side.
     ``bc`` overrides the boundary kinds (e.g. all periodic), ``bc_state`` the
-    raw per-side boundary values (e.g. a Riemann far-field pressure)."""
-    cfg = workloads.config(name, n_elem=n_elem)
+    raw per-side boundary values (e.g. a Riemann far-field pressure), ``order``
+    the polynomial degree."""
+    cfg = workloads.config(name, n_elem=n_elem, order=order)
     if bc is not None:
         cfg["bc"] = bc
         cfg["bc_prim"] = {}

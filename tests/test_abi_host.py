@@ -177,3 +177,21 @@ def test_order_one_meshes_and_their_host_checks():
         == dg2p.EUNSUPPORTED
     assert dg2p._lib.dg2p_kin_velocity_from_stream(m1.handle, fake, fake, None) == dg2p.EINVAL
     assert dg2p._lib.dg2p_kin_velocity_from_stream(m1.handle, None, fake, None) == dg2p.EINVAL
+
+
+def test_order_four_quadrilaterals():
+    """p = 4 on quadrilaterals (the paper's order for the wall-bounded runs):
+    25 nodes per element at the GLL points of degree 4, weights W_j =
+    w_a w_b J_x J_y, the face-ingredient buffer sized for 5 nodes per face;
+    hexahedra of order 4 are refused."""
+    m = dg2p.Mesh(2, (3, 2), (0.0, 0.0), (1.5, 1.0), order=4)
+    assert (m.nf, m.E, m.nn) == (7, 6, 25)
+    om = oracle.OracleMesh(2, 4, (3, 2), (0.0, 0.0), (1.5, 1.0))
+    assert np.abs(m.node_coords() - om.node_coords().numpy()).max() < 1e-15
+    assert np.abs(np.asarray(m.node_weights()) - om.node_weights().numpy()).max() < 1e-16
+    with pytest.raises(dg2p.Dg2pError) as ei:
+        dg2p.Mesh(3, (2, 2, 2), (0.0,) * 3, (1.0,) * 3, order=4)
+    assert ei.value.status == dg2p.EUNSUPPORTED
+    P = dg2p.make_params(workloads.config("drop2d")["params"])
+    m3 = dg2p.Mesh(2, (3, 2), (0.0, 0.0), (1.0, 1.0), order=3)
+    assert m.workspace_bytes(P, dg2p.OP_RHS) > m3.workspace_bytes(P, dg2p.OP_RHS)

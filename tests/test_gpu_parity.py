@@ -29,7 +29,9 @@ def _dg():
 
 
 def gpu_case(name, n_elem=None, variant=None, bc=None, bc_state=None, **over):
-    cfg, om, prm, U0 = oracle_setup(name, n_elem=n_elem, variant=variant, bc=bc, bc_state=bc_state, **over)
+    order = over.pop("order", 3)
+    cfg, om, prm, U0 = oracle_setup(name, n_elem=n_elem, variant=variant, bc=bc, bc_state=bc_state, order=order,
+                                    **over)
     dg = _dg()
     P = dg.make_params({**cfg["params"], **over})
     mesh = dg.mesh_from_config(dict(cfg, params={**cfg["params"], **over}), P)
