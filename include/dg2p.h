@@ -37,8 +37,10 @@
  *     synchronously and nothing is launched; dg2p_last_error() gives the
  *     detail (thread-local).  Non-physical states are never fatal inside a
  *     call: they are counted in dg2p_monitors.nonphys.
- *   - The two-phase model is implemented at polynomial order p = 3; the
- *     kinematic mode (dg2p_kin_*, re-initialisation excepted) also at p = 1
+ *   - The two-phase model is implemented at polynomial order p = 3, and at
+ *     p = 4 on quadrilaterals (FP64; no mixed forms, adjoint or kinematic
+ *     mode: the paper's order for its wall-bounded runs); the kinematic mode
+ *     (dg2p_kin_*, re-initialisation excepted) at p = 3 and p = 1
  *     (DG2P_EUNSUPPORTED else).  Nodes per element n = (p+1)^d, node
  *     j = sum_k a_k (p+1)^k; the layouts below write 4^d for p = 3.
  */
@@ -106,7 +108,8 @@ typedef enum {
  * Galerkin discretisation").  Entries beyond `dim` are ignored. */
 typedef struct {
   int dim;                   /* 1, 2 or 3 */
-  int order;                 /* polynomial degree p: 3, or 1 (kinematic mode only) */
+  int order;                 /* polynomial degree p: 3; 4 on quadrilaterals (FP64 two-phase path);
+                                1 (kinematic mode only) */
   int n_elem[3];             /* elements per axis, >= 1 */
   double lo[3], hi[3];       /* box corners, hi > lo */
   int bc[3][2];              /* dg2p_bc per axis and side (0 = low, 1 = high) */
