@@ -152,8 +152,9 @@ const char* dg2p_last_error(void);
 
 /* Create a mesh handle from a host descriptor.  Validates the descriptor
  * (EINVAL, also for 2^31 or more elements, or more than 2^40 nodes), rejects
- * p != 3 (EUNSUPPORTED).  Host only, allocates no device memory.  *out is
- * owned by the caller until dg2p_destroy_mesh. */
+ * orders other than 3, 1 and 4, and 4 outside quadrilaterals (EUNSUPPORTED;
+ * what each order runs is stated at the top).  Host only, allocates no device
+ * memory.  *out is owned by the caller until dg2p_destroy_mesh. */
 int dg2p_create_mesh(const dg2p_mesh_desc* desc /*host*/, dg2p_mesh* out /*host*/);
 
 /* Release a mesh handle (NULL is accepted). */
@@ -246,8 +247,11 @@ int dg2p_advance(dg2p_mesh m, const dg2p_params* p /*host*/, double* U /*device,
  * integrals, non-physical count, max |P - p_ref|, max |u - u_ref| -- and the
  * time-step rate of that state with its dt (the step that would follow;
  * *dt_fixed when given).  The last stage of each step emits the records that
- * one two-level reduction per step turns into these monitors and the next
- * dt.  Same states and dt as dg2p_advance.  A NaN anywhere in a state's rate
+ * are reduced into these monitors and the next dt: inside the next step's
+ * first stage on grids of 13 to 1024 element workgroups (p = 3), by two small
+ * kernels per step otherwise and for the last step.  The integrals' summation
+ * order differs between the two (rounding-level differences); the rest is
+ * exact.  Same states and dt as dg2p_advance.  A NaN anywhere in a state's rate
  * or monitors propagates (the dt of a state with a failed closure is NaN).
  * work: dg2p_workspace_size(DG2P_OP_ADVANCE) bytes. */
 int dg2p_advance_monitored(dg2p_mesh m, const dg2p_params* p /*host*/, double* U /*device, in/out*/, int n_steps,

@@ -440,6 +440,7 @@ void finalize_rate(const dg2p_mesh_s* m, const KArgs& A, const Work& w, long lon
 #endif
 constexpr long long FUSED_DT_MAX = DG2P_FUSED_DT_MAX;
 static_assert(FUSED_DT_MAX <= FUSED_RATE_MAX, "a first-stage workgroup reduces at most FUSED_RATE_MAX records");
+static_assert(RATE * FUSED_DT_MAX <= REC * REC2_MAX, "a monitored step's rate copy fits the second-level records");
 
 bool all_periodic(const dg2p_mesh_s* m) {
   for (int k = 0; k < m->dim; ++k)
@@ -852,8 +853,11 @@ namespace {
 // NULL) the last stage of every step writes 2-double rate records, from which
 // the next step's dt is reduced inside its first stage (small grids) or by
 // two small kernels; with them, the last stage writes the full 16-slot
-// records and one reduction per step yields the step's monitors and the next
-// dt.
+// records, from which the next step's first stage (small grids of at least
+// MON_SLOTS workgroups: a copy of their rate slots in rec2 gives dt, the first
+// MON_SLOTS workgroups reduce one other slot each) or one reduction per step
+// (two small kernels) yields the step's monitors and the next dt; the last
+// step's monitors always come from the latter.
 int advance_impl(const dg2p_mesh_s* m, const dg2p_params* p, double* U, int n_steps, double cfl,
                  const double* dt_fixed, double* t, double* dt_last, dg2p_monitors* mon, dg2p_monitors* mon_steps,
                  double p_ref, const double* u_ref, void* work, hipStream_t s) {
@@ -870,23 +874,31 @@ int advance_impl(const dg2p_mesh_s* m, const dg2p_params* p, double* U, int n_st
   const long long nrec = elem_blocks(m);
   // a first-stage workgroup reduces up to FUSED_RATE_PER_THREAD records per thread
   const long long fused_max = std::min<long long>(FUSED_DT_MAX, (long long)FUSED_RATE_PER_THREAD * elem_threads(m));
-  const bool fused = !mon_steps && nrec <= fused_max && !generic_order(m);
+  // (with per-step monitors, a grid of fewer than MON_SLOTS workgroups takes
+  // the separate reduction: its workgroups would reduce several slots each)
+  const bool fused = nrec <= fused_max && !generic_order(m) && (!mon_steps || nrec >= MON_SLOTS);
   A.cfl = cfl;
   A.hmin = min_h(m);
   A.nrate = nrec;
   launch_ingr(m, p, A, U, Ga, w.rec, s);
   for (int it = 0; it < n_steps; ++it) {
-    if (mon_steps && it > 0)
-      finalize(m, A, w, nrec, cfl, dt_fixed, dts, t, mon_steps + (it - 1), s);
-    else if (!fused)
-      finalize_rate(m, A, w, nrec, cfl, dt_fixed, dts, t, s);
+    const bool mon_prev = mon_steps && it > 0;  // monitors of the state after step it - 1
+    if (!fused) {
+      if (mon_prev) finalize(m, A, w, nrec, cfl, dt_fixed, dts, t, mon_steps + (it - 1), s);
+      else finalize_rate(m, A, w, nrec, cfl, dt_fixed, dts, t, s);
+    }
     KArgs B = A;
     StageIO io1{U, Ga, nullptr, w.U1, Gb, nullptr, dts};
     if (fused) {
-      io1.rate_in = w.rec;
+      // rate records: the ingredient pass's in rec, a monitored step's copy in rec2
+      io1.rate_in = mon_prev ? w.rec2 : w.rec;
       io1.dt_out = dts;
       io1.t = t;
       io1.dt_fixed = dt_fixed;
+      if (mon_prev) {
+        io1.mon_rec = w.rec;
+        io1.mon_out = mon_steps + (it - 1);
+      }
     }
     launch_stage(m, p, 1, 1, B, io1, s);
     B.rk_a = 0.75;
@@ -896,6 +908,7 @@ int advance_impl(const dg2p_mesh_s* m, const dg2p_params* p, double* U, int n_st
     B.rk_a = 1.0 / 3.0;
     B.rk_b = 2.0 / 3.0;
     StageIO io3{w.U2, Ga, U, U, Gb, w.rec, dts};
+    if (fused && mon_steps) io3.rate_out = w.rec2;
     launch_stage(m, p, 2, mon_steps ? 2 : 3, B, io3, s);
     double* tmp = Ga;
     Ga = Gb;

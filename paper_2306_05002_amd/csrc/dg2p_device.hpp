@@ -215,6 +215,12 @@ struct StageIO {
   double* dt_out;
   double* t;
   const double* dt_fixed;
+  // per-step monitors on a small grid: the last stage's full records also
+  // leave their rate slots in rate_out (the next first stage's rate_in), and
+  // that first stage reduces the full records mon_rec into *mon_out
+  double* rate_out;
+  const double* mon_rec;
+  dg2p_monitors* mon_out;
 };
 
 struct Prim {
@@ -695,9 +701,9 @@ __device__ __forceinline__ void fused_dt_load(const KArgs& A, const double* __re
 
 // Second half, at the stage combine (the first point that needs dt, so that
 // the workgroup barrier does not hold the waves back at entry): the maxima
-// over the workgroup's waves, and dt from them.
+// over the workgroup's waves, and the rate from them (dt = cfl / rate).
 template <int WT>
-__device__ __forceinline__ double fused_dt_finish(const KArgs& A, double (*sh)[WT / 64], int dim) {
+__device__ __forceinline__ double fused_rate_finish(const KArgs& A, double (*sh)[WT / 64], int dim) {
   __syncthreads();
   double w = sh[0][0];
   double nu = sh[1][0];
@@ -706,7 +712,7 @@ __device__ __forceinline__ double fused_dt_finish(const KArgs& A, double (*sh)[W
     w = nan_max(w, sh[0][i]);
     nu = nan_max(nu, sh[1][i]);
   }
-  return A.cfl / rate_of(w, nu, A.GammaEps, 16.0 * dim, A.hmin);
+  return rate_of(w, nu, A.GammaEps, 16.0 * dim, A.hmin);
 }
 
 // Per-node record contributions of a state (time-step rate and monitors), W
@@ -756,6 +762,9 @@ __device__ __forceinline__ double rec_combine(int slot, double a, double b) {
   if (slot == R_AMIN) return nan_min(a, b);
   if (slot == R_WAVE || slot == R_NU || slot == R_AMAX || slot == R_DEVP || slot == R_DEVU) return nan_max(a, b);
   return a + b;
+}
+__device__ __forceinline__ double rec_identity(int slot) {
+  return slot == R_AMIN ? INFINITY : (slot == R_AMAX ? -INFINITY : 0.0);
 }
 __device__ __forceinline__ double rec_wave(int slot, double v) {
   if (slot == R_AMIN) return wave_min(v);
@@ -809,9 +818,10 @@ __device__ __forceinline__ double wave_reduce_scatter(double* v) {
   }
 }
 
-// Workgroup reduction of per-lane records into rec[blk * REC + slot] (fixed order).
+// Workgroup reduction of per-lane records into rec[blk * REC + slot] (fixed
+// order); if rate != NULL its rate slots also into rate[blk * RATE + slot].
 template <int WT = BLOCK>
-__device__ __forceinline__ void block_record(double* v, double* rec, long long blk) {
+__device__ __forceinline__ void block_record(double* v, double* rec, long long blk, double* rate = nullptr) {
   __shared__ double sh[REC][WT / 64];
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -844,6 +854,7 @@ __device__ __forceinline__ void block_record(double* v, double* rec, long long b
 #pragma unroll
     for (int i = 1; i < WT / 64; ++i) x = rec_combine(s, x, sh[s][i]);
     rec[blk * REC + s] = x;
+    if (rate && s < RATE) rate[blk * RATE + s] = x;  // R_WAVE, R_NU
   }
 }
 
@@ -881,7 +892,7 @@ __device__ __forceinline__ void store_out(double* p, double v) {
 template <int DIM, bool VISC, bool WRITE_G, int REC_MODE, int PR>
 __device__ __forceinline__ void emit(const KArgs& A, const double* q, long long e, bool valid, int node,
                                      const int* ak, const Deriv<DIM, PR>& L, double* G, double* rec,
-                                     long long blk) {
+                                     long long blk, double* rate = nullptr) {
   constexpr int NN = 1 << (2 * DIM);
   constexpr int NFN = NN / 4;
   constexpr int C = VISC ? 1 + DIM : 1;
@@ -908,7 +919,7 @@ __device__ __forceinline__ void emit(const KArgs& A, const double* q, long long 
   if constexpr (REC_MODE == 2) {
     double v[REC];
     node_record<DIM, VISC>(A, q, p, node, valid, v);
-    block_record<ewg<DIM>()>(v, rec, blk);
+    block_record<ewg<DIM>()>(v, rec, blk, rate);
   } else if constexpr (REC_MODE == 1) {
     // time-step rate only: largest wave speed and kinematic viscosity
     double w = DIM * p.c;
@@ -1203,6 +1214,49 @@ __device__ __forceinline__ void spread_sym(const KArgs& A, int akk, const double
   }
 }
 
+// Per-step monitors of a small grid, in the first stage of the next step:
+// logical workgroup b reduces the record slots R_AMIN + b, R_AMIN + b +
+// nblocks, ... below R_INT + 8 over all A.nrate (<= FUSED_RATE_PER_THREAD WT)
+// records in a fixed order (each thread its records in turn, then the wave,
+// then the waves) and stores them into *mon; the rate and dt come from the
+// fused time step (workgroup 0).  Called by whole workgroups after their
+// stores; the loop bound is uniform.  The host fuses only grids of at least
+// MON_SLOTS workgroups, so that no workgroup reduces more than one slot.
+constexpr int MON_SLOTS = R_INT + 8 - R_AMIN;
+template <int WT, int NF>
+__device__ __forceinline__ void fused_monitor_slots(const KArgs& A, const double* __restrict__ rec,
+                                                    dg2p_monitors* mon, long long blk) {
+  __shared__ double sh[WT / 64];
+  for (long long s = R_AMIN + blk; s < R_INT + 8; s += A.nblocks) {
+    const int slot = (int)s;
+    const double id = rec_identity(slot);
+    double v[FUSED_RATE_PER_THREAD];
+#pragma unroll
+    for (int u = 0; u < FUSED_RATE_PER_THREAD; ++u) {
+      const long long r = threadIdx.x + u * WT;
+      v[u] = r < A.nrate ? rec[r * REC + slot] : id;
+    }
+    double acc = id;
+#pragma unroll
+    for (int u = 0; u < FUSED_RATE_PER_THREAD; ++u) acc = rec_combine(slot, acc, v[u]);
+    acc = rec_wave(slot, acc);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double x = sh[0];
+#pragma unroll
+      for (int i = 1; i < WT / 64; ++i) x = rec_combine(slot, x, sh[i]);
+      if (slot == R_AMIN) mon->min_alpha = x;
+      else if (slot == R_AMAX) mon->max_alpha = x;
+      else if (slot == R_BAD) mon->nonphys = (long long)x;
+      else if (slot == R_DEVP) mon->dev_p = x;
+      else if (slot == R_DEVU) mon->dev_u = x;
+      else mon->integral[slot - R_INT] = slot - R_INT < NF ? x : 0.0;
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Stage pass: residual of each element (volume terms, sources, all faces, SIPG
 // symmetric term), then MODE 0: store R; MODE 1: U_out = U_s + dt R;
@@ -1247,7 +1301,7 @@ __global__ __launch_bounds__(ewg<DIM>(), (min_waves<DIM, VISC>())) void k_stage(
   // first stage of a small grid: the rate records of the time step
   __shared__ double dt_lds[2][WT / 64];
   if constexpr (MODE == 1) {
-    if (io.dt_out && !io.dt_fixed) fused_dt_load<WT>(A, io.rate_in, dt_lds);
+    if (io.dt_out && (!io.dt_fixed || io.mon_out)) fused_dt_load<WT>(A, io.rate_in, dt_lds);
   }
   // element multi-index and face neighbours
   long long ec[3] = {0, 0, 0};
@@ -1566,10 +1620,16 @@ __global__ __launch_bounds__(ewg<DIM>(), (min_waves<DIM, VISC>())) void k_stage(
   double dt_fused = 0.0;
   if constexpr (MODE == 1) {
     if (io.dt_out) {
-      dt_fused = io.dt_fixed ? *io.dt_fixed : fused_dt_finish<WT>(A, dt_lds, DIM);
+      double rate = 0.0;
+      if (!io.dt_fixed || io.mon_out) rate = fused_rate_finish<WT>(A, dt_lds, DIM);
+      dt_fused = io.dt_fixed ? *io.dt_fixed : A.cfl / rate;
       if (blk == 0 && threadIdx.x == 0) {
         *io.dt_out = dt_fused;
         if (io.t) *io.t += dt_fused;
+        if (io.mon_out) {
+          io.mon_out->max_rate = rate;
+          io.mon_out->dt = dt_fused;
+        }
       }
     }
   }
@@ -1603,7 +1663,11 @@ __global__ __launch_bounds__(ewg<DIM>(), (min_waves<DIM, VISC>())) void k_stage(
       for (int f = 0; f < NF; ++f) store_out<DIM>(&io.Out[f * fs + o], uo[f]);
     }
     if constexpr (EPI > 0)
-      emit<DIM, VISC, true, (EPI == 2 ? 2 : (EPI == 3 ? 1 : 0)), PR>(A, uo, e, valid, node, ak, L, io.Gout, io.rec, blk);
+      emit<DIM, VISC, true, (EPI == 2 ? 2 : (EPI == 3 ? 1 : 0)), PR>(A, uo, e, valid, node, ak, L, io.Gout, io.rec,
+                                                                   blk, io.rate_out);
+    if constexpr (MODE == 1) {
+      if (io.mon_out) fused_monitor_slots<WT, NF>(A, io.mon_rec, io.mon_out, blk);
+    }
   }
 }
 
@@ -1704,9 +1768,6 @@ __global__ __launch_bounds__(BLOCK) void k_records(KArgs A, const double* __rest
 // ... (contiguous loads), then threads holding the same slot are combined
 // (lanes 16 and 32 apart in the wave, then the waves through LDS).  The
 // combination order is fixed, so the result is deterministic.
-__device__ __forceinline__ double rec_identity(int slot) {
-  return slot == R_AMIN ? INFINITY : (slot == R_AMAX ? -INFINITY : 0.0);
-}
 template <int NS, int NT>
 __device__ __forceinline__ void reduce_slots(const double* __restrict__ rec, long long lo, long long hi,
                                              double* red) {

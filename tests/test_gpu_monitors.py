@@ -26,7 +26,13 @@ def _case(name, ne):
     return cfg, om, prm, U0, mesh, P
 
 
-@pytest.mark.parametrize("name,ne", [("drop2d", (12, 10)), ("drop2d", (128, 128)), ("shock2d", (16, 8)),
+# Grids of fewer than 13 workgroups reduce each step's records in separate
+# kernels, larger ones (up to 1024 workgroups) in the next step's first stage:
+# drop2d 12x10 (8 workgroups of 16 quads), 16x13 (13, the smallest fused),
+# 16x16 (16), 128x128 (1024); shock2d 16x8 (8); rt3d 3x4x3 (36 one-hexahedron
+# workgroups, fused); drop1d 37 (1).
+@pytest.mark.parametrize("name,ne", [("drop2d", (12, 10)), ("drop2d", (16, 13)), ("drop2d", (16, 16)),
+                                     ("drop2d", (128, 128)), ("shock2d", (16, 8)),
                                      ("rt3d", (3, 4, 3)), ("drop1d", (37,))])
 def test_advance_monitored_every_step(name, ne):
     """Same states as dg2p_advance, bit for bit; row i of the per-step
@@ -80,12 +86,14 @@ def test_advance_monitored_every_step(name, ne):
     assert torch.equal(A, C)
 
 
-def test_failed_closure_makes_dt_nan_like_the_oracle():
+@pytest.mark.parametrize("ne", [(4, 4), (16, 16)])
+def test_failed_closure_makes_dt_nan_like_the_oracle(ne):
     """A node whose squared sound speed is negative (energy below the
     stiffened-gas floor) has a NaN wave speed: the reduced rate and dt are
     NaN on both sides (the reductions propagate NaN instead of skipping the
-    node), and a step taken from that state reports it in its monitors."""
-    cfg, om, prm, U0, mesh, P = _case("drop2d", (4, 4))
+    node), and a step taken from that state reports it in its monitors
+    (one workgroup: separate reduction; sixteen: fused into the stage)."""
+    cfg, om, prm, U0, mesh, P = _case("drop2d", ne)
     dg = _dg()
     U = U0.clone()
     U[4, 9, 9] = -50.0
@@ -101,3 +109,30 @@ def test_failed_closure_makes_dt_nan_like_the_oracle():
     assert math.isnan(float(t.cpu()))
     row = dg.decode_monitors(ms, mesh.nf)[0]
     assert row["nonphys"] > 0 and math.isnan(row["dt"])
+
+
+@pytest.mark.parametrize("ne", [(12, 10), (16, 16)])
+def test_advance_monitored_fixed_dt(ne):
+    """With a prescribed dt the per-step monitors still carry the state's
+    rate (equal to the stand-alone monitors') and report dt = dt_fixed; the
+    states equal dg2p_advance's with the same dt bit for bit."""
+    cfg, om, prm, U0, mesh, P = _case("drop2d", ne)
+    dg = _dg()
+    steps = 3
+    dtf = torch.tensor([0.3 * float(dg.max_dt(mesh, P, U0.cuda().contiguous(), cfl=0.1).cpu())],
+                       dtype=torch.float64, device="cuda")
+    A = U0.cuda().contiguous()
+    B = A.clone()
+    ms = torch.zeros(steps, dg.MONITOR_DOUBLES, dtype=torch.float64, device="cuda")
+    dg.advance_monitored(mesh, P, A, steps, ms, cfl=0.1, dt_fixed=dtf)
+    dg.advance(mesh, P, B, steps, cfl=0.1, dt_fixed=dtf)
+    assert torch.equal(A, B)
+    rows = dg.decode_monitors(ms, mesh.nf)
+    C = U0.cuda().contiguous()
+    for i in range(steps):
+        dg.rk_step(mesh, P, C, dtf)
+        ref = dg.monitors(mesh, P, C, p_ref=1.0)
+        assert rows[i]["dt"] == float(dtf.cpu())
+        assert abs(rows[i]["max_rate"] - ref["max_rate"]) <= 1e-14 * ref["max_rate"]
+        assert rows[i]["min_alpha"] == ref["min_alpha"] and rows[i]["max_alpha"] == ref["max_alpha"]
+    assert torch.equal(A, C)
