@@ -19,7 +19,9 @@ The JSON line also carries
                 launch stream during the timed region; HBM peak 8 TB/s.
                 `traffic` is the counter-measured HBM traffic per launch
                 recorded under profiles/ for the current kernel sources (null
-                if the sources changed since).
+                if the sources changed since).  Beside it: the bandwidth of a
+                plain device copy and the FP64 vector FMA rate, both measured
+                in the same run (dg2p_calibrate_fp64_fma).
   mixed_precision: FP32 and BF16 contraction forms on the 512 x 256 shock
                 (200 steps) and the 96^3 box (100 steps): per-field L2 / Linf
                 error against the FP64 path and speed.
@@ -97,6 +99,8 @@ def recorded(workload, what, key, src_hash):
 
 # a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles; 1024 SIMDs at 2.4 GHz
 VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4
+# FP64 vector FMA at that issue rate: 1024 SIMDs x 16 lanes x 2 flop x 2.4 GHz
+FP64_VFMA_NOMINAL_TFLOPS = 1024 * 16 * 2 * 2.4e9 / 1e12
 
 
 def oracle_state(cfg, pf):
@@ -628,6 +632,12 @@ def main():
         rl["frac_of_copy_kernel"] = rl["achieved"] / cbw
         if rl["traffic"] is not None:
             rl["traffic_gbs"] = rl["traffic"] / (rl["kernel_mean_ms"] * 1e-3) / 1e9
+    # the FP64 FMA rate this GPU sustains (the VALU issue fraction assumes the
+    # nominal 2.4 GHz; a lower measured rate means a lower sustained clock)
+    fma = dg2p.calibrate_fp64_fma()
+    rl["fp64_vfma_tflops_measured"] = fma
+    if rl["valu_issue"] is not None:
+        rl["valu_issue"]["frac_at_measured_fma_rate"] = rl["valu_issue"]["frac"] * FP64_VFMA_NOMINAL_TFLOPS / fma
     last = mon_rows[-1]
     monitors = {"per_step": True, "steps_with_nonphys": sum(1 for r in mon_rows if r["nonphys"]),
                 "last_step": {"nonphys": last["nonphys"], "min_alpha": last["min_alpha"],

@@ -383,6 +383,14 @@ typedef enum {
   DG2P_K_KIN_STAGE = 8    /* kinematic mode: residual + RK4 stage */
 } dg2p_kernel_kind;
 
+/* FP64 vector FMA issue rate of the device (a measurement utility, not a hot
+ * call): launches a calibration kernel of independent v_fma_f64 chains on
+ * `stream` five times, the first to warm up, waits for each (host blocking)
+ * and stores the best rate in TFLOP/s into *tflops (the nominal MI355X figure
+ * is 78.6: 1024 SIMDs x 16 lanes x 2 flop x 2.4 GHz; a lower rate here means
+ * a lower sustained clock).  Allocates no device memory. */
+int dg2p_calibrate_fp64_fma(double* tflops /*host*/, void* stream);
+
 /* Benchmark timing.  While enabled, every kernel the library launches is
  * bracketed by a pair of library-owned hipEvents recorded on its stream (at
  * most 8192 launches per enable; enabling resets the record).  The events

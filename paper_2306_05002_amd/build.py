@@ -68,7 +68,8 @@ def build(verbose=False, extra=()):
         if verbose and err.strip():
             print(err, file=sys.stderr)
     tmp = OUT + ".tmp"
-    rc, err = _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + [j[0] for j in jobs])
+    rc, err = _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + [j[0] for j in jobs] +
+                   ["-lrocprofiler-sdk-roctx"])
     if rc != 0:
         raise RuntimeError(f"link failed ({rc}):\n{err}")
     os.replace(tmp, OUT)

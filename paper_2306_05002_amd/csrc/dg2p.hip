@@ -5,6 +5,7 @@
 // device memory.
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -215,7 +216,42 @@ struct TimedLaunch {
   }
 };
 
+// A roctx range named after the entry point around each call that launches
+// work (shown by rocprofv3 --marker-trace beside the kernels it launched; a
+// cheap no-op without a tool attached).
+struct ApiRange {
+  explicit ApiRange(const char* name) { roctxRangePushA(name); }
+  ~ApiRange() { roctxRangePop(); }
+  ApiRange(const ApiRange&) = delete;
+  ApiRange& operator=(const ApiRange&) = delete;
+};
+#define DG2P_API_RANGE() ApiRange dg2p_api_range_(__func__)
+
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// FP64 FMA issue-rate calibration: every lane runs CALIB_CHAINS independent
+// multiply-add recurrences x <- a x + b (a = 1 - 1e-9, b = 1e-9 keep them
+// near 1), enough of them and enough waves to hide the FMA latency; the sum
+// is stored only if it equals `never` (never the case; sink is NULL), which
+// keeps the chains live.
+constexpr int CALIB_CHAINS = 8;
+constexpr int CALIB_THREADS = 256;
+constexpr int CALIB_WGS = 256 * 16;  // 16 four-wave workgroups per CU
+constexpr long long CALIB_ITERS = 4096;
+__global__ __launch_bounds__(CALIB_THREADS) void k_fma_calib(long long iters, double a, double b, double never,
+                                                              double* sink) {
+  double x[CALIB_CHAINS];
+#pragma unroll
+  for (int i = 0; i < CALIB_CHAINS; ++i) x[i] = 1.0 + 1e-3 * i + 1e-12 * threadIdx.x;
+  for (long long it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < CALIB_CHAINS; ++i) x[i] = fma(x[i], a, b);
+  }
+  double sum = 0.0;
+#pragma unroll
+  for (int i = 0; i < CALIB_CHAINS; ++i) sum += x[i];
+  if (sum == never && sink) sink[threadIdx.x] = sum;
+}
 
 bool viscous(const dg2p_params* p) { return p->mu[0] != 0.0 || p->mu[1] != 0.0; }
 // boundary code the stage kernels compile in: 0 = none (periodic mesh), 1 =
@@ -616,7 +652,7 @@ int noalloc_scratch(void** out) {
 
 extern "C" {
 
-const char* dg2p_version(void) { return "dg2p 0.1 (gfx950, p=3)"; }
+const char* dg2p_version(void) { return "dg2p 0.2 (gfx950; p = 3, p = 4 on quadrilaterals, p = 1 kinematic)"; }
 
 const char* dg2p_status_string(int status) {
   switch (status) {
@@ -653,6 +689,8 @@ int dg2p_create_mesh(const dg2p_mesh_desc* desc, dg2p_mesh* out) {
     }
     if ((desc->bc[k][0] == DG2P_BC_PERIODIC) != (desc->bc[k][1] == DG2P_BC_PERIODIC))
       return fail(DG2P_EINVAL, "periodic must be set on both sides of an axis");
+    // (checked before the product, which could otherwise overflow)
+    if (E > (1LL << 40) / desc->n_elem[k]) return fail(DG2P_EINVAL, "mesh too large");
     E *= desc->n_elem[k];
   }
   const int np1 = desc->order + 1;
@@ -730,6 +768,7 @@ int dg2p_workspace_size(dg2p_mesh m, const dg2p_params* p, int op, size_t* bytes
 }
 
 int dg2p_prim_to_cons(dg2p_mesh m, const dg2p_params* p, const double* prim, double* U, void* stream) {
+  DG2P_API_RANGE();
   g_last_error.clear();
   if (!m || !prim || !U) return fail(DG2P_EINVAL, "mesh, prim and U must be non-NULL");
   if (prim == U) return fail(DG2P_EINVAL, "prim and U may not alias");
@@ -750,6 +789,7 @@ int dg2p_prim_to_cons(dg2p_mesh m, const dg2p_params* p, const double* prim, dou
 
 int dg2p_prim_to_cons_vjp(dg2p_mesh m, const dg2p_params* p, const double* prim, const double* U_bar,
                           double* prim_bar, void* stream) {
+  DG2P_API_RANGE();
   g_last_error.clear();
   if (!m || !prim || !U_bar || !prim_bar) return fail(DG2P_EINVAL, "mesh, prim, U_bar and prim_bar must be non-NULL");
   if (prim_bar == prim || prim_bar == U_bar) return fail(DG2P_EINVAL, "prim_bar may not alias");
@@ -782,6 +822,7 @@ int dg2p_node_weights(dg2p_mesh m, double* W) {
 }
 
 int dg2p_rhs(dg2p_mesh m, const dg2p_params* p, const double* U, double* R, void* work, void* stream) {
+  DG2P_API_RANGE();
   g_last_error.clear();
   if (!m || !U || !R) return fail(DG2P_EINVAL, "mesh, U and R must be non-NULL");
   if (U == R) return fail(DG2P_EINVAL, "U and R may not alias");
@@ -800,6 +841,7 @@ int dg2p_rhs(dg2p_mesh m, const dg2p_params* p, const double* U, double* R, void
 
 int dg2p_max_dt(dg2p_mesh m, const dg2p_params* p, const double* U, double cfl, double* dt,
                 dg2p_monitors* mon, void* work, void* stream) {
+  DG2P_API_RANGE();
   g_last_error.clear();
   if (!m || !U || (!dt && !mon)) return fail(DG2P_EINVAL, "mesh, U and one of dt/mon must be non-NULL");
   if (!(cfl > 0.0)) return fail(DG2P_EINVAL, "cfl must be > 0");
@@ -816,6 +858,7 @@ int dg2p_max_dt(dg2p_mesh m, const dg2p_params* p, const double* U, double cfl, 
 }
 
 int dg2p_rk_step(dg2p_mesh m, const dg2p_params* p, double* U, const double* dt, void* work, void* stream) {
+  DG2P_API_RANGE();
   g_last_error.clear();
   if (!m || !U || !dt) return fail(DG2P_EINVAL, "mesh, U and dt must be non-NULL");
   int st = check_params(m, p);
@@ -827,6 +870,7 @@ int dg2p_rk_step(dg2p_mesh m, const dg2p_params* p, double* U, const double* dt,
 }
 
 int dg2p_rk_step_noalloc(dg2p_mesh m, const dg2p_params* p, double* U, const double* dt, void* stream) {
+  DG2P_API_RANGE();
   g_last_error.clear();
   if (!m || !U || !dt) return fail(DG2P_EINVAL, "mesh, U and dt must be non-NULL");
   int st = check_params(m, p);
@@ -941,6 +985,7 @@ extern "C" {
 int dg2p_advance(dg2p_mesh m, const dg2p_params* p, double* U, int n_steps, double cfl, const double* dt_fixed,
                  double* t, double* dt_last, dg2p_monitors* mon, double p_ref, const double* u_ref, void* work,
                  void* stream) {
+  DG2P_API_RANGE();
   g_last_error.clear();
   int st = advance_checks(m, p, U, n_steps, cfl, dt_fixed, work);
   if (st) return st;
@@ -951,6 +996,7 @@ int dg2p_advance(dg2p_mesh m, const dg2p_params* p, double* U, int n_steps, doub
 int dg2p_advance_monitored(dg2p_mesh m, const dg2p_params* p, double* U, int n_steps, double cfl,
                            const double* dt_fixed, double* t, double* dt_last, dg2p_monitors* mon_steps,
                            double p_ref, const double* u_ref, void* work, void* stream) {
+  DG2P_API_RANGE();
   g_last_error.clear();
   if (!mon_steps) return fail(DG2P_EINVAL, "mon_steps must be non-NULL");
   int st = advance_checks(m, p, U, n_steps, cfl, dt_fixed, work);
@@ -961,6 +1007,7 @@ int dg2p_advance_monitored(dg2p_mesh m, const dg2p_params* p, double* U, int n_s
 
 int dg2p_compute_monitors(dg2p_mesh m, const dg2p_params* p, const double* U, double p_ref, const double* u_ref,
                           dg2p_monitors* mon, void* work, void* stream) {
+  DG2P_API_RANGE();
   g_last_error.clear();
   if (!m || !U || !mon) return fail(DG2P_EINVAL, "mesh, U and mon must be non-NULL");
   int st = check_params(m, p);
@@ -980,6 +1027,7 @@ int dg2p_compute_monitors(dg2p_mesh m, const dg2p_params* p, const double* U, do
 
 int dg2p_rhs_vjp(dg2p_mesh m, const dg2p_params* p, const double* U, const double* R_bar, double* U_bar,
                  double* param_bar, void* work, void* stream) {
+  DG2P_API_RANGE();
   g_last_error.clear();
   if (!m || !U || !R_bar || !U_bar) return fail(DG2P_EINVAL, "mesh, U, R_bar and U_bar must be non-NULL");
   if (U_bar == U || U_bar == R_bar) return fail(DG2P_EINVAL, "U_bar may not alias U or R_bar");
@@ -1008,6 +1056,7 @@ int dg2p_rhs_vjp(dg2p_mesh m, const dg2p_params* p, const double* U, const doubl
 
 int dg2p_rk_step_vjp(dg2p_mesh m, const dg2p_params* p, const double* U_n, const double* dt, const double* U_np1_bar,
                      double* U_n_bar, double* param_bar, void* work, void* stream) {
+  DG2P_API_RANGE();
   g_last_error.clear();
   if (!m || !U_n || !dt || !U_np1_bar || !U_n_bar)
     return fail(DG2P_EINVAL, "mesh, U_n, dt, U_np1_bar and U_n_bar must be non-NULL");
@@ -1070,6 +1119,7 @@ int dg2p_kin_workspace_size(dg2p_mesh m, int op, size_t* bytes) {
 
 int dg2p_kin_rhs(dg2p_mesh m, const dg2p_kin_params* kp, const double* Phi, const double* u0, double t, double* R,
                  void* work, void* stream) {
+  DG2P_API_RANGE();
   g_last_error.clear();
   if (!m || !Phi || !u0 || !R) return fail(DG2P_EINVAL, "mesh, Phi, u0 and R must be non-NULL");
   if (R == Phi) return fail(DG2P_EINVAL, "R may not alias Phi");
@@ -1093,6 +1143,7 @@ int dg2p_kin_rhs(dg2p_mesh m, const dg2p_kin_params* kp, const double* Phi, cons
 
 int dg2p_kin_rk4(dg2p_mesh m, const dg2p_kin_params* kp, double* Phi, const double* u0, int n_steps, double t0,
                  double dt, void* work, void* stream) {
+  DG2P_API_RANGE();
   g_last_error.clear();
   if (!m || !Phi || !u0) return fail(DG2P_EINVAL, "mesh, Phi and u0 must be non-NULL");
   if (n_steps < 0) return fail(DG2P_EINVAL, "n_steps must be >= 0");
@@ -1139,6 +1190,7 @@ int dg2p_kin_rk4(dg2p_mesh m, const dg2p_kin_params* kp, double* Phi, const doub
 
 int dg2p_kin_reinit(dg2p_mesh m, const dg2p_kin_params* kp, double* Phi, int n_iter, double nu, double dtau,
                     void* work, void* stream) {
+  DG2P_API_RANGE();
   g_last_error.clear();
   if (!m || !Phi) return fail(DG2P_EINVAL, "mesh and Phi must be non-NULL");
   if (n_iter < 0) return fail(DG2P_EINVAL, "n_iter must be >= 0");
@@ -1201,6 +1253,7 @@ int dg2p_kin_reinit_params(dg2p_mesh m, double cfl, double* nu, double* dtau) {
 }
 
 int dg2p_kin_velocity_from_stream(dg2p_mesh m, const double* S, double* u0, void* stream) {
+  DG2P_API_RANGE();
   g_last_error.clear();
   if (!m || !S || !u0) return fail(DG2P_EINVAL, "mesh, S and u0 must be non-NULL");
   if (S == u0) return fail(DG2P_EINVAL, "u0 may not alias S");
@@ -1224,6 +1277,7 @@ int dg2p_kin_velocity_from_stream(dg2p_mesh m, const double* S, double* u0, void
 
 int dg2p_kin_max_dt(dg2p_mesh m, const dg2p_kin_params* kp, const double* u0, double cfl, double* dt, void* work,
                     void* stream) {
+  DG2P_API_RANGE();
   g_last_error.clear();
   if (!m || !u0 || !dt) return fail(DG2P_EINVAL, "mesh, u0 and dt must be non-NULL");
   if (!(cfl > 0.0)) return fail(DG2P_EINVAL, "cfl must be > 0");
@@ -1259,6 +1313,7 @@ int dg2p_kin_max_dt(dg2p_mesh m, const dg2p_kin_params* kp, const double* u0, do
 }
 
 int dg2p_kin_errors(dg2p_mesh m, const double* phi, const double* phi0, double* out, void* work, void* stream) {
+  DG2P_API_RANGE();
   g_last_error.clear();
   if (!m || !phi || !phi0 || !out) return fail(DG2P_EINVAL, "mesh, phi, phi0 and out must be non-NULL");
   int st = check_ws(work, kin_work_bytes(m, DG2P_OP_KIN_AUX));
@@ -1282,6 +1337,38 @@ int dg2p_kin_errors(dg2p_mesh m, const double* phi, const double* phi0, double* 
   }
   hipLaunchKernelGGL(k_kin_sum, dim3(1), dim3(FIN_THREADS), 0, s, rec, nb, 3, out);
   return hip_check(hipGetLastError(), "kin_errors launch");
+}
+
+int dg2p_calibrate_fp64_fma(double* tflops, void* stream) {
+  DG2P_API_RANGE();
+  g_last_error.clear();
+  if (!tflops) return fail(DG2P_EINVAL, "tflops must be non-NULL");
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(DG2P_EHIP, "hipEventCreate failed");
+  }
+  const dim3 grid(CALIB_WGS), block(CALIB_THREADS);
+  double best_ms = 0.0;
+  int st = DG2P_OK;
+  for (int rep = 0; rep < 4 && st == DG2P_OK; ++rep) {
+    (void)hipEventRecord(e0, s);
+    hipLaunchKernelGGL(k_fma_calib, grid, block, 0, s, CALIB_ITERS, 1.0 - 1e-9, 1e-9, -1.0,
+                       static_cast<double*>(nullptr));
+    (void)hipEventRecord(e1, s);
+    st = hip_check(hipEventSynchronize(e1), "fma calibration");
+    float ms = 0.0f;
+    if (st == DG2P_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && rep > 0 && (best_ms == 0.0 || ms < best_ms))
+      best_ms = ms;  // the first launch warms the clocks up and is not counted
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != DG2P_OK) return st;
+  if (!(best_ms > 0.0)) return fail(DG2P_EHIP, "fma calibration: no elapsed time");
+  const double flop = 2.0 * CALIB_CHAINS * (double)CALIB_ITERS * CALIB_WGS * CALIB_THREADS;
+  *tflops = flop / (best_ms * 1e-3) / 1e12;
+  return DG2P_OK;
 }
 
 int dg2p_timing_enable(int on) {

@@ -92,6 +92,7 @@ _SIG = {
     "dg2p_kin_reinit": ([_vp, ctypes.POINTER(KinParams), _dp, _i, _d, _d, _vp, _vp], _i),
     "dg2p_kin_errors": ([_vp, _dp, _dp, _dp, _vp, _vp], _i),
     "dg2p_kin_velocity_from_stream": ([_vp, _dp, _dp, _vp], _i),
+    "dg2p_calibrate_fp64_fma": ([ctypes.POINTER(_d), _vp], _i),
     "dg2p_timing_enable": ([_i], _i),
     "dg2p_timing_read": ([_i, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_longlong)], _i),
 }
@@ -379,6 +380,13 @@ def require_physical(mon, what="state"):
     if mon["nonphys"] > 0:
         raise Dg2pError(ENONPHYS, f"{what}: {mon['nonphys']} non-physical nodes")
     return mon
+
+
+def calibrate_fp64_fma(stream=None):
+    """Measured FP64 vector FMA rate of the device in TFLOP/s (host blocking)."""
+    v = ctypes.c_double()
+    _check(_lib.dg2p_calibrate_fp64_fma(ctypes.byref(v), _stream(stream)), "dg2p_calibrate_fp64_fma")
+    return v.value
 
 
 def timing_enable(on=True):

@@ -35,6 +35,19 @@ def test_version_and_status_strings():
     assert dg2p._lib.dg2p_status_string(-1).decode() == "DG2P_EINVAL"
 
 
+def test_fma_calibration_rejects_null_output():
+    """Argument checks come before any device call."""
+    assert dg2p._lib.dg2p_calibrate_fp64_fma(None, None) == dg2p.EINVAL
+
+
+def test_library_links_the_roctx_ranges():
+    """The entry points open roctx ranges (rocprofv3 --marker-trace): the
+    library depends on the ROCm roctx library."""
+    import subprocess
+    out = subprocess.run(["readelf", "-d", dg2p.LIB_PATH], capture_output=True, text=True).stdout
+    assert "librocprofiler-sdk-roctx" in out
+
+
 @pytest.mark.parametrize("bad", ["dim", "order", "n_elem", "box", "bc", "periodic_pair", "riemann_pressure",
                                  "elem_count"])
 def test_create_mesh_rejects_bad_descriptors(bad):
