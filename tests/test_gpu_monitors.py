@@ -136,3 +136,34 @@ def test_advance_monitored_fixed_dt(ne):
         assert abs(rows[i]["max_rate"] - ref["max_rate"]) <= 1e-14 * ref["max_rate"]
         assert rows[i]["min_alpha"] == ref["min_alpha"] and rows[i]["max_alpha"] == ref["max_alpha"]
     assert torch.equal(A, C)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_advance_monitored_mixed_precision_fused(precision):
+    """The mixed contraction forms on a grid whose monitors are reduced in
+    the next first stage (16 workgroups): states equal dg2p_advance's bit for
+    bit, and each row equals the stand-alone monitors of the same state
+    (integrals to rounding)."""
+    cfg, om, prm, U0, mesh, _ = _case("drop2d", (16, 16))
+    dg = _dg()
+    P = dg.make_params(cfg["params"], precision=precision)
+    steps = 3
+    A = U0.cuda().contiguous()
+    B = A.clone()
+    ms = torch.zeros(steps, dg.MONITOR_DOUBLES, dtype=torch.float64, device="cuda")
+    dg.advance_monitored(mesh, P, A, steps, ms, cfl=0.1)
+    dg.advance(mesh, P, B, steps, cfl=0.1)
+    assert torch.equal(A, B)
+    rows = dg.decode_monitors(ms, mesh.nf)
+    C = U0.cuda().contiguous()
+    for i in range(steps):
+        dt = dg.max_dt(mesh, P, C, cfl=0.1)
+        dg.rk_step(mesh, P, C, dt)
+        ref = dg.monitors(mesh, P, C)
+        assert rows[i]["min_alpha"] == ref["min_alpha"] and rows[i]["max_alpha"] == ref["max_alpha"]
+        assert rows[i]["nonphys"] == ref["nonphys"]
+        assert abs(rows[i]["max_rate"] - ref["max_rate"]) <= 1e-14 * ref["max_rate"]
+        for f in range(mesh.nf):
+            scale = float(torch.abs(C[f]).max()) * sum(mesh.node_weights()) * mesh.E + 1e-300
+            assert abs(rows[i]["integral"][f] - ref["integral"][f]) <= 1e-14 * scale
+    assert torch.equal(A, C)

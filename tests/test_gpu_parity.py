@@ -328,6 +328,28 @@ def test_advance_fixed_dt():
     assert max(state_errors(A.cpu(), Uo, prm, om.d)) <= 1e-12
 
 
+@pytest.mark.parametrize("name,ne", [("drop2d", (6, 5)), ("rt3d", (3, 2, 4))])
+def test_advance_zero_steps(name, ne):
+    """n_steps = 0 is the degenerate run: the state and the time stay as
+    they were, a monitored call writes no step row, and the final monitors
+    are those of the unchanged state (equal to the stand-alone monitors)."""
+    cfg, om, prm, U0, mesh, P = gpu_case(name, ne)
+    dg = _dg()
+    A = U0.cuda().contiguous()
+    t = torch.full((1,), 0.25, dtype=torch.float64, device="cuda")
+    mon = torch.zeros(dg.MONITOR_DOUBLES, dtype=torch.float64, device="cuda")
+    dg.advance(mesh, P, A, 0, cfl=0.1, t=t, mon=mon)
+    assert torch.equal(A.cpu(), U0) and float(t.cpu()) == 0.25
+    got = dg.decode_monitors(mon.view(1, -1), mesh.nf)[0]
+    ref = dg.monitors(mesh, P, A)
+    assert got["min_alpha"] == ref["min_alpha"] and got["max_alpha"] == ref["max_alpha"]
+    assert got["integral"] == ref["integral"] and got["max_rate"] == ref["max_rate"]
+    rows = torch.full((2, dg.MONITOR_DOUBLES), -7.0, dtype=torch.float64, device="cuda")
+    dg.advance_monitored(mesh, P, A, 0, rows, cfl=0.1, t=t)
+    assert torch.equal(A.cpu(), U0) and float(t.cpu()) == 0.25
+    assert bool((rows == -7.0).all())
+
+
 @pytest.mark.parametrize("ne", [(128, 128), (136, 136)])
 def test_full_grid_step_against_the_oracle(ne):
     """One step of dg2p_advance on the full 128 x 128 droplet (1024 rate
