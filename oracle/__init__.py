@@ -23,6 +23,9 @@ Modules
   residual  the semi-discrete DG operator dU/dt = R(U)
   stepper   time-step rule, SSP-RK3 and monitors
   adjoint   loss, checkpointed rollout and autograd gradients
+  kinematic the phase field and level set under a prescribed velocity (RK4,
+            L1 and mass errors), the level-set re-initialisation, and the
+            velocity of a nodal stream function
 
 Pinning status (what fixes each function other than itself) is listed in the
 tests under ``tests/test_oracle_*.py``.  The readings of the paper's silent
