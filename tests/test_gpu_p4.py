@@ -106,6 +106,29 @@ def test_p4_advance_and_monitors(name, ne):
     assert abs(mg["max_rate"] - mo["max_rate"]) <= 1e-11 * mo["max_rate"]
 
 
+@pytest.mark.parametrize("name,ne", [("bubble2d", (16, 32)), ("rt2d", (16, 64))])
+def test_p4_bench_grid_step_against_the_oracle(name, ne):
+    """The grids the benchmark runs at p = 4 (rising bubble 16 x 32, RT
+    16 x 64, at CFL 0.05), in its launch configuration: one dg2p_advance step
+    (device dt) against the oracle's step from the same state, dt to 1e-14
+    and every field to 1e-12.  The level set is perturbed as in the residual
+    tests (the bubble's cone tip sits on a GLL node of this grid)."""
+    cfg, om, prm, U0, mesh, P = case(name, ne)
+    dg = _dg()
+    torch.manual_seed(11)
+    U = U0.clone()
+    U[3 + om.d + 1] += 1e-3 * torch.randn(U[0].shape, dtype=torch.float64)
+    dto = oracle.max_dt(U, om, prm, cfl=0.05)
+    Uo = oracle.rk_step(U, dto, om, prm)
+    A = U.cuda().contiguous()
+    last = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dg.advance(mesh, P, A, 1, cfl=0.05, dt_last=last)
+    assert abs(float(last.cpu()) - dto) <= 1e-14 * dto
+    errs = state_errors(A.cpu(), Uo, prm, om.d)
+    print(name, ["%.1e" % e for e in errs])
+    assert max(errs) <= TOL, errs
+
+
 def test_p4_rejects_what_it_does_not_run():
     """p = 4: FP64 two-phase path only (no mixed forms, adjoint or kinematic
     mode), and quadrilaterals only."""
