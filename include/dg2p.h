@@ -248,8 +248,8 @@ int dg2p_advance(dg2p_mesh m, const dg2p_params* p /*host*/, double* U /*device,
  * time-step rate of that state with its dt (the step that would follow;
  * *dt_fixed when given).  The last stage of each step emits the records that
  * are reduced into these monitors and the next dt: inside the next step's
- * first stage on grids of 13 to 1024 element workgroups (p = 3), by two small
- * kernels per step otherwise and for the last step.  The integrals' summation
+ * first stage on grids of 13 to 1024 element workgroups (p = 3; 13 to 256 at
+ * p = 4), by two small kernels per step otherwise and for the last step.  The integrals' summation
  * order differs between the two (rounding-level differences); the rest is
  * exact.  Same states and dt as dg2p_advance.  A NaN anywhere in a state's rate
  * or monitors propagates (the dt of a state with a failed closure is NaN).

@@ -920,7 +920,7 @@ int advance_impl(const dg2p_mesh_s* m, const dg2p_params* p, double* U, int n_st
   const long long fused_max = std::min<long long>(FUSED_DT_MAX, (long long)FUSED_RATE_PER_THREAD * elem_threads(m));
   // (with per-step monitors, a grid of fewer than MON_SLOTS workgroups takes
   // the separate reduction: its workgroups would reduce several slots each)
-  const bool fused = nrec <= fused_max && !generic_order(m) && (!mon_steps || nrec >= MON_SLOTS);
+  const bool fused = nrec <= fused_max && (!mon_steps || nrec >= MON_SLOTS);
   A.cfl = cfl;
   A.hmin = min_h(m);
   A.nrate = nrec;

@@ -702,8 +702,9 @@ __device__ __forceinline__ void fused_dt_load(const KArgs& A, const double* __re
 // Second half, at the stage combine (the first point that needs dt, so that
 // the workgroup barrier does not hold the waves back at entry): the maxima
 // over the workgroup's waves, and the rate from them (dt = cfl / rate).
+// pdim = (p+1)^2 d of the time-step rule.
 template <int WT>
-__device__ __forceinline__ double fused_rate_finish(const KArgs& A, double (*sh)[WT / 64], int dim) {
+__device__ __forceinline__ double fused_rate_finish(const KArgs& A, double (*sh)[WT / 64], double pdim) {
   __syncthreads();
   double w = sh[0][0];
   double nu = sh[1][0];
@@ -712,7 +713,7 @@ __device__ __forceinline__ double fused_rate_finish(const KArgs& A, double (*sh)
     w = nan_max(w, sh[0][i]);
     nu = nan_max(nu, sh[1][i]);
   }
-  return rate_of(w, nu, A.GammaEps, 16.0 * dim, A.hmin);
+  return rate_of(w, nu, A.GammaEps, pdim, A.hmin);
 }
 
 // Per-node record contributions of a state (time-step rate and monitors), W
@@ -1621,7 +1622,7 @@ __global__ __launch_bounds__(ewg<DIM>(), (min_waves<DIM, VISC>())) void k_stage(
   if constexpr (MODE == 1) {
     if (io.dt_out) {
       double rate = 0.0;
-      if (!io.dt_fixed || io.mon_out) rate = fused_rate_finish<WT>(A, dt_lds, DIM);
+      if (!io.dt_fixed || io.mon_out) rate = fused_rate_finish<WT>(A, dt_lds, 16.0 * DIM);
       dt_fused = io.dt_fixed ? *io.dt_fixed : A.cfl / rate;
       if (blk == 0 && threadIdx.x == 0) {
         *io.dt_out = dt_fused;

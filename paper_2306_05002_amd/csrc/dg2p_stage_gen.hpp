@@ -152,7 +152,8 @@ __device__ __forceinline__ void gen_gradients(const KArgs& A, const double* q, c
 // element's face nodes) into G, and its records (REC_MODE 1: rate, 2: all).
 template <int P, bool VISC, bool WRITE_G, int REC_MODE>
 __device__ __forceinline__ void gen_emit(const KArgs& A, const double* q, long long e, bool valid,
-                                         const GenLane<P>& Gl, double* G, double* rec, long long blk) {
+                                         const GenLane<P>& Gl, double* G, double* rec, long long blk,
+                                         double* rate = nullptr) {
   constexpr int C = VISC ? 3 : 1;
   constexpr int NFN = P + 1;
   Prim p;
@@ -180,7 +181,7 @@ __device__ __forceinline__ void gen_emit(const KArgs& A, const double* q, long l
     double v[REC];
     const double W = gen_w<P>(A, Gl.ax) * gen_w<P>(A, Gl.ay) * A.J[0] * A.J[1];
     node_record_w<2, VISC>(A, q, p, W, valid, v);
-    block_record<64>(v, rec, blk);
+    block_record<64>(v, rec, blk, rate);
   } else if constexpr (REC_MODE == 1) {
     double w = 2.0 * p.c + fabs(p.u[0]) + fabs(p.u[1]);
     double nu = 0.0;
@@ -217,7 +218,8 @@ __global__ __launch_bounds__(64) void k_ingredients_g(KArgs A, const double* __r
   gen_emit<P, VISC, true, 1>(A, q, e, valid, Gl, G, rec, blk);
 }
 
-// Stage pass (modes and epilogues as k_stage; no fused time step).
+// Stage pass (modes, epilogues and the fused time step and monitors of a
+// small grid as k_stage).
 template <int P, bool VISC, bool CSF, int BCK, int MODE, int EPI>
 __global__ __launch_bounds__(64) void k_stage_g(KArgs A, StageIO io) {
   constexpr int NP = P + 1;
@@ -236,7 +238,14 @@ __global__ __launch_bounds__(64) void k_stage_g(KArgs A, StageIO io) {
 #pragma unroll
   for (int f = 0; f < NF; ++f) q[f] = Us[(f * A.E + e) * NN + Gl.node];
   double dt_in = 0.0;
-  if constexpr (MODE != 0) dt_in = *io.dt;
+  if constexpr (MODE != 0) {
+    if (!(MODE == 1 && io.dt_out)) dt_in = *io.dt;
+  }
+  // first stage of a small grid: the rate records of the time step
+  __shared__ double dt_lds[2][1];
+  if constexpr (MODE == 1) {
+    if (io.dt_out && (!io.dt_fixed || io.mon_out)) fused_dt_load<64>(A, io.rate_in, dt_lds);
+  }
   Prim pr;
   closure<2>(A, q, pr);
   Grad<2, VISC> g;
@@ -376,6 +385,23 @@ __global__ __launch_bounds__(64) void k_stage_g(KArgs A, StageIO io) {
     }
   }
 
+  // the fused time step of a small grid (uniform branch)
+  double dt_fused = 0.0;
+  if constexpr (MODE == 1) {
+    if (io.dt_out) {
+      double rate = 0.0;
+      if (!io.dt_fixed || io.mon_out) rate = fused_rate_finish<64>(A, dt_lds, (double)(NP * NP * 2));
+      dt_fused = io.dt_fixed ? *io.dt_fixed : A.cfl / rate;
+      if (blk == 0 && threadIdx.x == 0) {
+        *io.dt_out = dt_fused;
+        if (io.t) *io.t += dt_fused;
+        if (io.mon_out) {
+          io.mon_out->max_rate = rate;
+          io.mon_out->dt = dt_fused;
+        }
+      }
+    }
+  }
   const long long o = e * NN + Gl.node;
   const long long fs = A.E * NN;
   if constexpr (MODE == 0) {
@@ -384,7 +410,7 @@ __global__ __launch_bounds__(64) void k_stage_g(KArgs A, StageIO io) {
       for (int f = 0; f < NF; ++f) io.Out[f * fs + o] = R[f];
     }
   } else {
-    const double dt = dt_in;
+    const double dt = (MODE == 1 && io.dt_out) ? dt_fused : dt_in;
     double uo[NF];
     if constexpr (MODE == 1) {
 #pragma unroll
@@ -398,7 +424,11 @@ __global__ __launch_bounds__(64) void k_stage_g(KArgs A, StageIO io) {
       for (int f = 0; f < NF; ++f) io.Out[f * fs + o] = uo[f];
     }
     if constexpr (EPI > 0)
-      gen_emit<P, VISC, true, (EPI == 2 ? 2 : (EPI == 3 ? 1 : 0))>(A, uo, e, valid, Gl, io.Gout, io.rec, blk);
+      gen_emit<P, VISC, true, (EPI == 2 ? 2 : (EPI == 3 ? 1 : 0))>(A, uo, e, valid, Gl, io.Gout, io.rec, blk,
+                                                                  io.rate_out);
+    if constexpr (MODE == 1) {
+      if (io.mon_out) fused_monitor_slots<64, NF>(A, io.mon_rec, io.mon_out, blk);
+    }
   }
 }
 

@@ -2,7 +2,7 @@
 rising-bubble runs) on the GPU through the C ABI, against the FP64 oracle at
 p = 4: residuals under every boundary kind with the viscous, surface-tension
 and gravity terms, RK steps and the device time step, the monitors, and
-dg2p_advance bit for bit against dg2p_rk_step.  Metric and bar as in
+dg2p_advance / dg2p_advance_monitored bit for bit against dg2p_rk_step.  Metric and bar as in
 test_gpu_parity.py (1e-12 per field)."""
 
 import pytest
@@ -127,6 +127,47 @@ def test_p4_bench_grid_step_against_the_oracle(name, ne):
     errs = state_errors(A.cpu(), Uo, prm, om.d)
     print(name, ["%.1e" % e for e in errs])
     assert max(errs) <= TOL, errs
+
+
+# one-wave workgroups of two quads: bubble2d 6x5 (15 workgroups) and 16x32
+# (256, the largest grid whose first stage reduces the records itself) take
+# the fused reduction of dt and the monitors; rt2d 3x7 (11) fuses dt only,
+# 16x64 (512) neither
+@pytest.mark.parametrize("name,ne", [("bubble2d", (6, 5)), ("bubble2d", (16, 32)), ("rt2d", (3, 7)),
+                                     ("rt2d", (16, 64))])
+def test_p4_advance_monitored_every_step(name, ne):
+    """dg2p_advance_monitored at p = 4: the same states and time as
+    dg2p_advance bit for bit, and every step's monitors equal to the
+    stand-alone monitors of that step's state (alpha range and non-physical
+    count exactly, rate and dt to rounding, integrals up to the summation
+    order)."""
+    cfg, om, prm, U0, mesh, P = case(name, ne)
+    dg = _dg()
+    steps = 3
+    A = U0.cuda().contiguous()
+    B = A.clone()
+    ms = torch.zeros(steps, dg.MONITOR_DOUBLES, dtype=torch.float64, device="cuda")
+    tA = torch.zeros(1, dtype=torch.float64, device="cuda")
+    tB = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dg.advance_monitored(mesh, P, A, steps, ms, cfl=0.05, t=tA)
+    dg.advance(mesh, P, B, steps, cfl=0.05, t=tB)
+    assert torch.equal(A, B) and torch.equal(tA, tB)
+    rows = dg.decode_monitors(ms, mesh.nf)
+    C = U0.cuda().contiguous()
+    for i in range(steps):
+        dt = dg.max_dt(mesh, P, C, cfl=0.05)
+        dg.rk_step(mesh, P, C, dt)
+        ref = dg.monitors(mesh, P, C)
+        got = rows[i]
+        assert got["min_alpha"] == ref["min_alpha"] and got["max_alpha"] == ref["max_alpha"]
+        assert got["nonphys"] == ref["nonphys"] == 0
+        assert abs(got["max_rate"] - ref["max_rate"]) <= 1e-14 * ref["max_rate"]
+        dtr = float(dg.max_dt(mesh, P, C, cfl=0.05).cpu())
+        assert abs(got["dt"] - dtr) <= 1e-14 * dtr
+        for f in range(mesh.nf):
+            scale = float(torch.abs(C[f]).max()) * sum(mesh.node_weights()) * mesh.E + 1e-300
+            assert abs(got["integral"][f] - ref["integral"][f]) <= 1e-14 * scale, (i, f)
+    assert torch.equal(A, C)
 
 
 def test_p4_rejects_what_it_does_not_run():
