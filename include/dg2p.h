@@ -263,9 +263,11 @@ int dg2p_advance_monitored(dg2p_mesh m, const dg2p_params* p /*host*/, double* U
 /* Vector-Jacobian product of dg2p_rhs (hand-written reverse mode):
  * U_bar = (dR/dU)^T R_bar, overwritten; if param_bar != NULL,
  * param_bar[0] += <R_bar, dR/dsigma> (surface tension).  Non-smooth points:
- * d max(a,b) splits 1/2, 1/2 at ties, d|x|/dx = 0 at 0.  FP64 and periodic
- * meshes only (DG2P_EUNSUPPORTED otherwise).  U, R_bar, U_bar: device
- * [N_f][E][4^d]; U_bar may not alias.  work: DG2P_OP_RHS_VJP bytes. */
+ * d max(a,b) splits 1/2, 1/2 at ties, d|x|/dx = 0 at 0.  Every boundary
+ * kind (the ghost traces are reversed into the boundary element's own
+ * values).  FP64 and p = 3 only (DG2P_EUNSUPPORTED otherwise).  U, R_bar,
+ * U_bar: device [N_f][E][4^d]; U_bar may not alias.  work: DG2P_OP_RHS_VJP
+ * bytes. */
 int dg2p_rhs_vjp(dg2p_mesh m, const dg2p_params* p /*host*/, const double* U /*device*/,
                  const double* R_bar /*device*/, double* U_bar /*device, out*/,
                  double* param_bar /*device, nullable, accumulated*/, void* work /*device*/, void* stream);

@@ -490,13 +490,14 @@ void residual_vjp(const dg2p_mesh_s* m, const dg2p_params* p, const KArgs& A, co
                   hipStream_t s) {
   const bool visc = viscous(p);
   const bool csf = p->sigma != 0.0 || sigb != nullptr;
+  const bool walls = !all_periodic(m);
   VjpIO io{U, G, Rb, T, FB, rec, Ub, accumulate};
   {
     TimedLaunch t(DG2P_K_VJP_LOCAL, s);
     switch (m->dim) {
-      case 1: launch_vjp_dim<1>(visc, csf, A, io, s); break;
-      case 2: launch_vjp_dim<2>(visc, csf, A, io, s); break;
-      default: launch_vjp_dim<3>(visc, csf, A, io, s); break;
+      case 1: launch_vjp_dim<1>(visc, csf, walls, A, io, s); break;
+      case 2: launch_vjp_dim<2>(visc, csf, walls, A, io, s); break;
+      default: launch_vjp_dim<3>(visc, csf, walls, A, io, s); break;
     }
   }
   if (sigb && csf) hipLaunchKernelGGL(k_sum_add, dim3(1), dim3(BLOCK), 0, s, rec, A.nblocks, sigb);
@@ -1034,7 +1035,6 @@ int dg2p_rhs_vjp(dg2p_mesh m, const dg2p_params* p, const double* U, const doubl
   int st = check_params(m, p);
   if (st) return st;
   if (p->precision != DG2P_FP64) return fail(DG2P_EUNSUPPORTED, "the adjoint is FP64 only");
-  if (!all_periodic(m)) return fail(DG2P_EUNSUPPORTED, "the adjoint supports periodic meshes only");
   if (m->desc.order != 3) return fail(DG2P_EUNSUPPORTED, "the adjoint is implemented for p = 3");
   st = check_ws(work, work_bytes(m, p, DG2P_OP_RHS_VJP));
   if (st) return st;
@@ -1064,7 +1064,6 @@ int dg2p_rk_step_vjp(dg2p_mesh m, const dg2p_params* p, const double* U_n, const
   int st = check_params(m, p);
   if (st) return st;
   if (p->precision != DG2P_FP64) return fail(DG2P_EUNSUPPORTED, "the adjoint is FP64 only");
-  if (!all_periodic(m)) return fail(DG2P_EUNSUPPORTED, "the adjoint supports periodic meshes only");
   if (m->desc.order != 3) return fail(DG2P_EUNSUPPORTED, "the adjoint is implemented for p = 3");
   st = check_ws(work, work_bytes(m, p, DG2P_OP_RK_STEP_VJP));
   if (st) return st;

@@ -17,8 +17,10 @@
 //
 // No atomics, fixed reduction order: deterministic.  Non-smooth points follow
 // the convention d max(a, b) = 1/2, 1/2 at ties and d|x|/dx = 0 at x = 0.
-// Periodic meshes only (other boundary kinds return DG2P_EUNSUPPORTED from the
-// host entry points); FP64 only.
+// Boundary faces: the ghost trace is a function of the element's own trace
+// and gradients (ghost_fwd, as in the forward face evaluation), so its
+// cotangents go back to the element's own values (ghost_rev) instead of into
+// the face buffer, and the gather pass skips those faces.  FP64 only.
 
 #pragma once
 
@@ -261,7 +263,177 @@ __device__ __forceinline__ void block_sum(double v, double* rec, long long blk) 
   }
 }
 
-template <int DIM, bool VISC, bool CSF>
+// Ghost trace of a boundary face (axis kd, side, boundary kind) from the
+// element's own trace q, pr and gradient quantities g: the neighbour state qe,
+// its a.e_kd (aek) and viscous traction (tek), built as in face_flux.
+template <int DIM, bool VISC>
+__device__ __forceinline__ void ghost_fwd(const KArgs& A, int kd, int side, int kind, const double* q,
+                                          const Prim& pr, const GradF<DIM, VISC>& g, double* qe, double& aek,
+                                          double* tek) {
+  constexpr int NF = DIM + 5;
+  const double sm = side ? 1.0 : -1.0;
+#pragma unroll
+  for (int f = 0; f < NF; ++f) qe[f] = q[f];
+  aek = g.a[kd];
+  if constexpr (VISC) {
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) tek[j] = g.mu * g.S[j][kd];
+  }
+  if (kind == DG2P_BC_SLIP_WALL || kind == DG2P_BC_NO_SLIP) {
+    const bool slip = kind == DG2P_BC_SLIP_WALL;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j)
+      if (!slip || j == kd) qe[2 + j] = -q[2 + j];
+    aek = -g.a[kd];
+    if constexpr (VISC) {
+#pragma unroll
+      for (int j = 0; j < DIM; ++j)
+        if (slip && j != kd) tek[j] = -tek[j];
+    }
+  } else if (kind == DG2P_BC_RIEMANN) {
+    const double al = q[3 + DIM];
+    const double xi = al * A.xi1 + (1.0 - al) * A.xi2;
+    const double pim = al * A.pi1 + (1.0 - al) * A.pi2;
+    const double Pb = A.bcs[kd][side][0];
+    const double un = sm * pr.u[kd];
+    const double cfar = sqrt(((1.0 + xi) * Pb + pim) / (xi * pr.rho));
+    const double jout = un + 2.0 * xi * pr.c;
+    const double jin = -2.0 * xi * cfar;
+    const double unb = 0.5 * (jout + jin);
+    const double cb = (jout - jin) / (4.0 * xi);
+    const double Pg = (xi * pr.rho * cb * cb - pim) / (1.0 + xi);
+    double k2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+      const double ug = pr.u[j] + (j == kd ? sm * (unb - un) : 0.0);
+      qe[2 + j] = pr.rho * ug;
+      k2 += ug * ug;
+    }
+    qe[2 + DIM] = xi * Pg + pim + 0.5 * pr.rho * k2;
+  } else if (kind == DG2P_BC_DIRICHLET) {
+#pragma unroll
+    for (int f = 0; f < 4 + DIM; ++f) qe[f] = A.bcs[kd][side][f];
+    const double ag = qe[3 + DIM];
+    aek = A.Gamma * (A.eps * g.gA[kd] - (ag * (1.0 - ag)) * g.nh[kd]);
+    if constexpr (VISC) {
+      const double mug = A.mu1 * ag + A.mu2 * (1.0 - ag);
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) tek[j] = mug * g.S[j][kd];
+    }
+  }
+}
+
+// Reverse of ghost_fwd: the cotangents qeb, aekb, tekb of the ghost trace
+// added to the element's own trace (qb, and pb for the primitives the
+// Riemann ghost is built from) and gradient quantities (ab, gAb, nhb, Sb, mub).
+template <int DIM, bool VISC>
+__device__ __forceinline__ void ghost_rev(const KArgs& A, int kd, int side, int kind, const double* q,
+                                          const Prim& pr, const GradF<DIM, VISC>& g, const double* qeb,
+                                          double aekb, const double* tekb, double* qb, PrimBar& pb, double* ab,
+                                          double* gAb, double* nhb, double (*Sb)[VISC ? DIM : 1], double& mub) {
+  constexpr int NF = DIM + 5;
+  const double sm = side ? 1.0 : -1.0;
+  if (kind == DG2P_BC_DIRICHLET) {
+    // prescribed (q1, q2, rho u, rho E, alpha); psi and the gradients interior
+    qb[4 + DIM] += qeb[4 + DIM];
+    const double ag = A.bcs[kd][side][3 + DIM];
+    gAb[kd] += A.Gamma * A.eps * aekb;
+    nhb[kd] -= A.Gamma * (ag * (1.0 - ag)) * aekb;
+    if constexpr (VISC) {
+      const double mug = A.mu1 * ag + A.mu2 * (1.0 - ag);
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) Sb[j][kd] += mug * tekb[j];
+    }
+    return;
+  }
+  const bool mirror = kind == DG2P_BC_SLIP_WALL || kind == DG2P_BC_NO_SLIP;
+  const bool slip = kind == DG2P_BC_SLIP_WALL;
+  // fields copied from the interior (all but the momentum and energy of a
+  // Riemann ghost; momentum components with their mirror sign)
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    const bool mom = f >= 2 && f < 2 + DIM;
+    if (kind == DG2P_BC_RIEMANN && (mom || f == 2 + DIM)) continue;
+    double sgn = 1.0;
+    if (mirror && mom && (!slip || f - 2 == kd)) sgn = -1.0;
+    qb[f] += sgn * qeb[f];
+  }
+  ab[kd] += mirror ? -aekb : aekb;
+  if constexpr (VISC) {
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+      const double ts = (slip && j != kd) ? -1.0 : 1.0;
+      mub += ts * g.S[j][kd] * tekb[j];
+      Sb[j][kd] += ts * g.mu * tekb[j];
+    }
+  }
+  if (kind == DG2P_BC_RIEMANN) {
+    // recompute the forward values
+    const double al = q[3 + DIM];
+    const double xi = al * A.xi1 + (1.0 - al) * A.xi2;
+    const double pim = al * A.pi1 + (1.0 - al) * A.pi2;
+    const double Pb = A.bcs[kd][side][0];
+    const double un = sm * pr.u[kd];
+    const double N = (1.0 + xi) * Pb + pim, Dn = xi * pr.rho;
+    const double cfar = sqrt(N / Dn);
+    const double jout = un + 2.0 * xi * pr.c;
+    const double jin = -2.0 * xi * cfar;
+    const double unb = 0.5 * (jout + jin);
+    const double cb = (jout - jin) / (4.0 * xi);
+    const double Pg = (xi * pr.rho * cb * cb - pim) / (1.0 + xi);
+    double ug[DIM], k2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+      ug[j] = pr.u[j] + (j == kd ? sm * (unb - un) : 0.0);
+      k2 += ug[j] * ug[j];
+    }
+    // reverse: qe[2 + j] = rho ug_j, qe[2 + DIM] = xi Pg + pim + rho k2 / 2
+    const double Eb = qeb[2 + DIM];
+    double rhob = 0.5 * k2 * Eb, xib = Pg * Eb, pimb = Eb;
+    const double Pgb = xi * Eb;
+    double unbb = 0.0, unb_ = 0.0;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+      const double ugb = pr.rho * qeb[2 + j] + pr.rho * ug[j] * Eb;
+      rhob += ug[j] * qeb[2 + j];
+      pb.u[j] += ugb;
+      if (j == kd) {
+        unbb += sm * ugb;
+        unb_ -= sm * ugb;
+      }
+    }
+    // Pg = (xi rho cb^2 - pim) / (1 + xi)
+    xib += Pgb * (pr.rho * cb * cb + pim) / ((1.0 + xi) * (1.0 + xi));
+    rhob += Pgb * xi * cb * cb / (1.0 + xi);
+    const double cbb = Pgb * 2.0 * xi * pr.rho * cb / (1.0 + xi);
+    pimb -= Pgb / (1.0 + xi);
+    // cb = (jout - jin) / (4 xi), unb = (jout + jin) / 2
+    double joutb = cbb / (4.0 * xi) + 0.5 * unbb;
+    double jinb = -cbb / (4.0 * xi) + 0.5 * unbb;
+    xib -= cbb * cb / xi;
+    // jin = -2 xi cfar, jout = un + 2 xi c
+    xib -= 2.0 * cfar * jinb;
+    const double cfarb = -2.0 * xi * jinb;
+    unb_ += joutb;
+    xib += 2.0 * pr.c * joutb;
+    pb.c += 2.0 * xi * joutb;
+    // cfar = sqrt(N / Dn)
+    const double Xb = cfarb / (2.0 * cfar);
+    const double Nb = Xb / Dn;
+    const double Dnb = -Xb * N / (Dn * Dn);
+    xib += Pb * Nb + pr.rho * Dnb;
+    pimb += Nb;
+    rhob += xi * Dnb;
+    // un = sm u_kd
+    pb.u[kd] += sm * unb_;
+    pb.rho += rhob;
+    qb[3 + DIM] += (A.xi1 - A.xi2) * xib + (A.pi1 - A.pi2) * pimb;
+  }
+}
+
+// WALLS: the mesh has non-periodic sides (the ghost code is compiled in only
+// then, so that the periodic kernels keep their registers).
+template <int DIM, bool VISC, bool CSF, bool WALLS>
 __global__ __launch_bounds__(ewg<DIM>()) void k_vjp_local(KArgs A, VjpIO io) {
   constexpr int NN = 1 << (2 * DIM);
   constexpr int EPW = 64 / NN;
@@ -335,8 +507,15 @@ __global__ __launch_bounds__(ewg<DIM>()) void k_vjp_local(KArgs A, VjpIO io) {
       const int side = akk == 3;
       const double sm = side ? 1.0 : -1.0;
       long long c = ec[k] + (side ? 1 : -1);
-      if (c < 0) c = A.N[k] - 1;
-      if (c >= A.N[k]) c = 0;
+      bool bnd = false;
+      if (c < 0 || c >= A.N[k]) {
+        if (!WALLS || bc_kind(A, k, side) == DG2P_BC_PERIODIC) {
+          c = (c < 0) ? A.N[k] - 1 : 0;
+        } else {
+          bnd = true;  // ghost: the loads below read the element itself (in bounds, replaced)
+          c = ec[k];
+        }
+      }
       long long estr = 1;
 #pragma unroll
       for (int kk = 0; kk < k; ++kk) estr *= A.N[kk];
@@ -353,12 +532,17 @@ __global__ __launch_bounds__(ewg<DIM>()) void k_vjp_local(KArgs A, VjpIO io) {
 #pragma unroll
         for (int j = 0; j < DIM; ++j) tek[j] = io.Gin[(gb + (long long)(1 + j) * A.E + en) * NFN + fn];
       }
+      const int kind = bnd ? bc_kind(A, k, side) : DG2P_BC_PERIODIC;
+      double aek_ = aek;
+      if constexpr (WALLS) {
+        if (bnd) ghost_fwd<DIM, VISC>(A, k, side, kind, q, pr, g, qe, aek_, tek);
+      }
       Prim pe;
       closure<DIM>(A, qe, pe);
       const double umI = sm * pr.u[k], umE = sm * pe.u[k];
       const double lA = fabs(umI) + pr.c, lB = fabs(umE) + pe.c;
       const double lam = fmax(lA, lB);
-      const double amI = sm * g.a[k], amE = sm * aek;
+      const double amI = sm * g.a[k], amE = sm * aek_;
       const double alI = q[3 + DIM], alE = qe[3 + DIM];
       const double jump = alI - alE;
       const double ahat = 0.5 * (amI + amE) - A.pen[k] * A.GammaEps * jump;
@@ -473,7 +657,9 @@ __global__ __launch_bounds__(ewg<DIM>()) void k_vjp_local(KArgs A, VjpIO io) {
       pb.u[k] += sm * umIb;
       pbe.u[k] += sm * umEb;
       closure_rev<DIM>(A, qe, pe, pbe, qeb);
-      if (valid) {
+      if (WALLS && bnd) {
+        ghost_rev<DIM, VISC>(A, k, side, kind, q, pr, g, qeb, aekb, tekb, qb, pb, ab, gAb, nhb, Sb, mub);
+      } else if (valid) {
         const long long fb = (long long)((2 * k + side) * CF) * A.E;
 #pragma unroll
         for (int f = 0; f < NF; ++f) io.FB[(fb + (long long)f * A.E + e) * NFN + fn] = qeb[f];
@@ -572,7 +758,7 @@ __global__ __launch_bounds__(ewg<DIM>()) void k_vjp_local(KArgs A, VjpIO io) {
   if constexpr (CSF) block_sum<ewg<DIM>()>(sigb, io.rec, blk);
 }
 
-template <int DIM, bool VISC>
+template <int DIM, bool VISC, bool WALLS>
 __global__ __launch_bounds__(ewg<DIM>()) void k_vjp_gather(KArgs A, VjpIO io) {
   constexpr int NN = 1 << (2 * DIM);
   constexpr int EPW = 64 / NN;
@@ -622,8 +808,11 @@ __global__ __launch_bounds__(ewg<DIM>()) void k_vjp_gather(KArgs A, VjpIO io) {
     if (akk != 0 && akk != 3) continue;
     const int side = akk == 3;
     long long c = ec[k] + (side ? 1 : -1);
-    if (c < 0) c = A.N[k] - 1;
-    if (c >= A.N[k]) c = 0;
+    if (c < 0 || c >= A.N[k]) {
+      // a boundary face has no neighbour: its ghost was reversed locally
+      if (WALLS && bc_kind(A, k, side) != DG2P_BC_PERIODIC) continue;
+      c = (c < 0) ? A.N[k] - 1 : 0;
+    }
     long long estr = 1;
 #pragma unroll
     for (int kk = 0; kk < k; ++kk) estr *= A.N[kk];

@@ -39,6 +39,6 @@ void launch_records_gen(int order, bool visc, unsigned blocks, const KArgs& A, c
 
 // Residual VJP passes (k_vjp_local, k_vjp_gather) of dimension DIM.
 template <int DIM>
-void launch_vjp_dim(bool visc, bool csf, const KArgs& A, const VjpIO& io, hipStream_t s);
+void launch_vjp_dim(bool visc, bool csf, bool walls, const KArgs& A, const VjpIO& io, hipStream_t s);
 
 }  // namespace dg2p
