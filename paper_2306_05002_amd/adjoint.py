@@ -91,8 +91,10 @@ class AdjointProblem:
     unperturbed initial state.
     """
 
-    def __init__(self, n_elem=None, n_steps=None, checkpoint_every=None, cfl=0.1):
+    def __init__(self, n_elem=None, n_steps=None, checkpoint_every=None, cfl=0.1, bc=None):
         cfg = workloads.config("adjoint2d", n_elem=n_elem)
+        if bc is not None:   # boundary kinds per axis, e.g. [("no_slip", "no_slip"), ("slip_wall", "slip_wall")]
+            cfg["bc"] = [tuple(b) for b in bc]
         self.cfg = cfg
         self.d = cfg["dim"]
         self.n_steps = cfg["steps"] if n_steps is None else n_steps

@@ -47,6 +47,21 @@ def test_adjoint_fd_reduced():
     assert worst < 1e-6, worst
 
 
+def test_adjoint_fd_walls():
+    """The same gradient with extrapolation in x and slip walls in y (the
+    ghosts' reverse), against central differences.  (The workload's
+    translating droplet driven into walls on both axes loses positivity
+    within ten steps; the residual VJP of the other kinds is tested against
+    the oracle in test_gpu_parity.py.)"""
+    prob = _adj().AdjointProblem(n_elem=(12, 12), n_steps=16, checkpoint_every=5,
+                                 bc=[("extrapolate", "extrapolate"), ("slip_wall", "slip_wall")])
+    L0, worst, rows = fd_agreement(prob, n_dir=8)
+    for r in rows:
+        print("dir %2d fd % .12e adj % .12e rel %.2e" % r)
+    assert L0 > 0.0
+    assert worst < 1e-6, worst
+
+
 def test_adjoint_matches_oracle_autograd():
     """Same problem on both sides, each with its own forward, target run and
     frozen dt; the oracle differentiates its rollout with torch.autograd."""
