@@ -269,8 +269,11 @@ int bc_class(const dg2p_mesh_s* m) {
 }
 
 size_t g_bytes(const dg2p_mesh_s* m, const dg2p_params* p) {
+  // components per face node, stored in pairs when more than one (GLay); the
+  // p = 4 kernels use C of them
   const int C = viscous(p) ? 1 + m->dim : 1;
-  return align256(sizeof(double) * (size_t)(2 * m->dim) * C * (size_t)m->E * m->nfn);
+  const int CP = C == 1 ? 1 : 2 * ((C + 1) / 2);
+  return align256(sizeof(double) * (size_t)(2 * m->dim) * CP * (size_t)m->E * m->nfn);
 }
 size_t state_bytes(const dg2p_mesh_s* m) {
   return align256(sizeof(double) * (size_t)m->nf * (size_t)m->E * m->nn);

@@ -525,12 +525,13 @@ __global__ __launch_bounds__(ewg<DIM>()) void k_vjp_local(KArgs A, VjpIO io) {
       double qe[NF];
 #pragma unroll
       for (int f = 0; f < NF; ++f) qe[f] = io.U[(f * A.E + en) * NN + nodee];
-      const long long gb = (long long)((2 * k + 1 - side) * C) * A.E;
-      const double aek = io.Gin[(gb + en) * NFN + fn];
+      double gv[2 * GLay<DIM, VISC>::P];
+      g_read<DIM, VISC>(A, io.Gin, 2 * k + 1 - side, en, fn, gv);
+      const double aek = gv[0];
       double tek[DIM];
       if constexpr (VISC) {
 #pragma unroll
-        for (int j = 0; j < DIM; ++j) tek[j] = io.Gin[(gb + (long long)(1 + j) * A.E + en) * NFN + fn];
+        for (int j = 0; j < DIM; ++j) tek[j] = gv[1 + j];
       }
       const int kind = bnd ? bc_kind(A, k, side) : DG2P_BC_PERIODIC;
       double aek_ = aek;

@@ -888,15 +888,52 @@ __device__ __forceinline__ void store_out(double* p, double v) {
   if constexpr (DIM == 3) __builtin_nontemporal_store(v, p);
   else *p = v;
 }
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+template <int DIM>
+__device__ __forceinline__ void store_out2(double* p, dbl2 v) {
+  if constexpr (DIM == 3) __builtin_nontemporal_store(v, reinterpret_cast<dbl2*>(p));
+  else *reinterpret_cast<dbl2*>(p) = v;
+}
+
+// Layout of the face-ingredient buffer G.  Face slot s = 2k + side of an
+// element holds, at each of its NFN face nodes, C components: a.e_k, then
+// (viscous) the traction mu S[j][k], j < d.  They are stored in pairs (W = 2;
+// one value when C = 1), so that a lane moves its node's ingredients with one
+// 16-byte access per pair: G[((s P + pr) E + e) NFN W + fn W + i] holds
+// component pr W + i (a pair of a plane holds NFN W contiguous doubles).
+template <int DIM, bool VISC>
+struct GLay {
+  static constexpr int C = VISC ? 1 + DIM : 1;
+  static constexpr int W = C == 1 ? 1 : 2;
+  static constexpr int P = (C + W - 1) / W;
+  static constexpr int NFN = (1 << (2 * DIM)) / 4;
+  __device__ static long long at(long long E, int slot, int pr, long long e, int fn) {
+    return ((long long)(slot * P + pr) * E + e) * (NFN * W) + (long long)fn * W;
+  }
+};
+// The ingredients of face slot `slot`, node fn of element e: v[0] = a.e_k,
+// v[1 + j] = the traction components.
+template <int DIM, bool VISC>
+__device__ __forceinline__ void g_read(const KArgs& A, const double* __restrict__ G, int slot, long long e, int fn,
+                                       double* v) {
+  using L = GLay<DIM, VISC>;
+  if constexpr (L::W == 2) {
+#pragma unroll
+    for (int pr = 0; pr < L::P; ++pr) {
+      const dbl2 x = *reinterpret_cast<const dbl2*>(G + L::at(A.E, slot, pr, e, fn));
+      v[2 * pr] = x.x;
+      v[2 * pr + 1] = x.y;
+    }
+  } else {
+    v[0] = G[L::at(A.E, slot, 0, e, fn)];
+  }
+}
 
 // ---- epilogue: face ingredients and records of a state held per lane ----------------
 template <int DIM, bool VISC, bool WRITE_G, int REC_MODE, int PR>
 __device__ __forceinline__ void emit(const KArgs& A, const double* q, long long e, bool valid, int node,
                                      const int* ak, const Deriv<DIM, PR>& L, double* G, double* rec,
                                      long long blk, double* rate = nullptr) {
-  constexpr int NN = 1 << (2 * DIM);
-  constexpr int NFN = NN / 4;
-  constexpr int C = VISC ? 1 + DIM : 1;
   Prim p;
   closure<DIM>(A, q, p);
   if constexpr (WRITE_G) {
@@ -908,11 +945,19 @@ __device__ __forceinline__ void emit(const KArgs& A, const double* q, long long 
         if (ak[k] != 0 && ak[k] != 3) continue;
         const int side = ak[k] == 3;
         const int fn = face_index(node, k);
-        const long long base = (long long)((2 * k + side) * C) * A.E;
-        store_out<DIM>(&G[(base + e) * NFN + fn], g.a[k]);
-        if constexpr (VISC) {
+        using GL = GLay<DIM, VISC>;
+        if constexpr (GL::W == 2) {
+          double v[2 * GL::P];
+          v[0] = g.a[k];
 #pragma unroll
-          for (int j = 0; j < DIM; ++j) store_out<DIM>(&G[(base + (long long)(1 + j) * A.E + e) * NFN + fn], g.mu * g.S[j][k]);
+          for (int j = 0; j < DIM; ++j) v[1 + j] = g.mu * g.S[j][k];
+#pragma unroll
+          for (int i = 1 + DIM; i < 2 * GL::P; ++i) v[i] = 0.0;
+#pragma unroll
+          for (int pr = 0; pr < GL::P; ++pr)
+            store_out2<DIM>(&G[GL::at(A.E, 2 * k + side, pr, e, fn)], dbl2{v[2 * pr], v[2 * pr + 1]});
+        } else {
+          store_out<DIM>(&G[GL::at(A.E, 2 * k + side, 0, e, fn)], g.a[k]);
         }
       }
     }
@@ -1013,14 +1058,13 @@ __device__ __forceinline__ void face_load(const KArgs& A, const double* __restri
                                           int fn, double* qn, double& an, double* tn) {
   constexpr int NN = 1 << (2 * DIM);
   constexpr int NF = DIM + 5;
-  constexpr int C = VISC ? 1 + DIM : 1;
-  constexpr int NFN = NN / 4;
 #pragma unroll
   for (int f = 0; f < NF; ++f) qn[f] = Us[(f * A.E + en) * NN + nodee];
-  const long long gb = (long long)((2 * kd + 1 - side) * C) * A.E;
-  an = Gin[(gb + en) * NFN + fn];
+  double v[2 * GLay<DIM, VISC>::P];
+  g_read<DIM, VISC>(A, Gin, 2 * kd + 1 - side, en, fn, v);
+  an = v[0];
 #pragma unroll
-  for (int j = 0; j < DIM; ++j) tn[j] = VISC ? Gin[(gb + (long long)(1 + j) * A.E + en) * NFN + fn] : 0.0;
+  for (int j = 0; j < DIM; ++j) tn[j] = VISC ? v[1 + j] : 0.0;
 }
 
 // Contributions of one face node of an element to that node: Rc[f] (lift
@@ -1385,7 +1429,6 @@ __global__ __launch_bounds__(ewg<DIM>(), (min_waves<DIM, VISC>())) void k_stage(
   __shared__ __attribute__((aligned(16))) double zt_lds[Z_LDS ? WT / 64 : 1][Z_LDS ? 3 : 1][Z_LDS ? 128 : 1];
   __shared__ __attribute__((aligned(16))) double un_lds[UN_LDS ? WT / 64 : 1][UN_LDS ? NF : 1][UN_LDS ? NN : 1];
   if constexpr (Z_LDS) {
-    constexpr int C = VISC ? 1 + DIM : 1;
     const int w = threadIdx.x >> 6;
     const int sd = (lane >> 3) & 1, part = lane & 7, cc = lane >> 4;
     // z-neighbour on side sd (uniform in the wave: one element per wave); a
@@ -1409,8 +1452,26 @@ __global__ __launch_bounds__(ewg<DIM>(), (min_waves<DIM, VISC>())) void k_stage(
                                        (__attribute__((address_space(3))) void*)&zt_lds[w][t][0], 16, 0, 0);
     }
     {
-      const int comp = cc < C ? cc : C - 1;
-      const double* src = io.Gin + ((long long)((5 - sd) * C + comp) * A.E + en) * (NN / 4) + 2 * part;
+      // the face ingredients: viscous, lane l = 32 pr + 16 s + node fetches
+      // the pair pr of its node on side s (slice 2 at double 64 pr + 32 s +
+      // 2 node); inviscid, lane l fetches doubles 2p, 2p + 1 of side s as the
+      // traces do (lanes 16-63 repeat lanes 0-15; slice 2 at 16 s + node)
+      using GL = GLay<DIM, VISC>;
+      const int sg = VISC ? ((lane >> 4) & 1) : sd;
+      long long eng = e;
+      {
+        long long c = ec[2] + (sg ? 1 : -1);
+        bool bnd = false;
+        if (c < 0 || c >= A.N[2]) {
+          if (BCK == 0 || bc_kind(A, 2, sg) == DG2P_BC_PERIODIC)
+            c = (c < 0) ? A.N[2] - 1 : 0;
+          else
+            bnd = true;
+        }
+        if (!bnd) eng = e + (c - ec[2]) * ((long long)A.N[0] * A.N[1]);
+      }
+      const double* src = VISC ? io.Gin + GL::at(A.E, 5 - sg, lane >> 5, eng, lane & 15)
+                               : io.Gin + GL::at(A.E, 5 - sg, 0, eng, 2 * part);
       __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src),
                                        (__attribute__((address_space(3))) void*)&zt_lds[w][2][0], 16, 0, 0);
     }
@@ -1600,9 +1661,17 @@ __global__ __launch_bounds__(ewg<DIM>(), (min_waves<DIM, VISC>())) void k_stage(
           const int slot = 16 * (akk == 3) + (node & 15);
 #pragma unroll
           for (int f = 0; f < NF; ++f) qk[f] = zt_lds[w][f >> 2][32 * (f & 3) + slot];
-          ank = zt_lds[w][2][slot];
+          if constexpr (VISC) {
+            // component c of (side, node) at 64 (c / 2) + 32 side + 2 node + c % 2
+            const int b = 32 * (akk == 3) + 2 * (node & 15);
+            ank = zt_lds[w][2][b];
 #pragma unroll
-          for (int j = 0; j < DIM; ++j) tk[j] = VISC ? zt_lds[w][2][32 * (1 + j) + slot] : 0.0;
+            for (int j = 0; j < DIM; ++j) tk[j] = zt_lds[w][2][64 * ((1 + j) >> 1) + b + ((1 + j) & 1)];
+          } else {
+            ank = zt_lds[w][2][slot];
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) tk[j] = 0.0;
+          }
         } else {
           face_load<DIM, VISC>(A, Us, Gin, k, akk == 3, enb[k], node + (3 - 2 * akk) * S, face_index(node, k), qk,
                                ank, tk);
