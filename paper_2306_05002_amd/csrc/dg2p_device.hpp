@@ -899,8 +899,11 @@ __device__ __forceinline__ void store_out2(double* p, dbl2 v) {
 // element holds, at each of its NFN face nodes, C components: a.e_k, then
 // (viscous) the traction mu S[j][k], j < d.  They are stored in pairs (W = 2;
 // one value when C = 1), so that a lane moves its node's ingredients with one
-// 16-byte access per pair: G[((s P + pr) E + e) NFN W + fn W + i] holds
-// component pr W + i (a pair of a plane holds NFN W contiguous doubles).
+// 16-byte access per pair, and element by element:
+// G[((e 2d + s) P + pr) NFN W + fn W + i] holds component pr W + i.  An
+// element's ingredients are one contiguous block (3 KB for a viscous
+// hexahedron), so a pass writes G as one stream instead of one per face slot
+// and component.
 template <int DIM, bool VISC>
 struct GLay {
   static constexpr int C = VISC ? 1 + DIM : 1;
@@ -908,7 +911,8 @@ struct GLay {
   static constexpr int P = (C + W - 1) / W;
   static constexpr int NFN = (1 << (2 * DIM)) / 4;
   __device__ static long long at(long long E, int slot, int pr, long long e, int fn) {
-    return ((long long)(slot * P + pr) * E + e) * (NFN * W) + (long long)fn * W;
+    (void)E;
+    return ((e * (2 * DIM) + slot) * P + pr) * (NFN * W) + (long long)fn * W;
   }
 };
 // The ingredients of face slot `slot`, node fn of element e: v[0] = a.e_k,
