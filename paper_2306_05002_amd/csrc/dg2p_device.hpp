@@ -160,6 +160,8 @@ struct KArgs {
   long long nblocks;    // logical workgroups of the element passes
   long long xcd_chunk;  // logical workgroups per XCD slab
   int N[3];
+  // hexahedron stage pass: x-y tile of its traversal order (see tiled_coords)
+  int tile[2];
   int bc[3][2];
   // the same boundary kinds, 3 bits per side at bit 3 (2k + side): read with
   // a per-lane side as a shift of a kernel argument (bc_kind), not as an
@@ -872,11 +874,56 @@ __device__ __forceinline__ void elem_coords(const KArgs& A, long long e, long lo
   }
 }
 
+// Side of the x-y tiles of the hexahedron stage pass's traversal order.
+#ifndef DG2P_TILE_3D
+#define DG2P_TILE_3D 16
+#endif
+
 // Logical workgroup of this physical workgroup (XCD-aware order); -1 if padding.
 __device__ __forceinline__ long long logical_block(const KArgs& A) {
   const long long i = blockIdx.x;
   const long long lb = (i & 7) * A.xcd_chunk + (i >> 3);
   return lb < A.nblocks ? lb : -1;
+}
+
+// Element (multi-index ec) of logical workgroup lb of the hexahedron stage
+// pass (one element each).  The x-y plane is cut into tiles of A.tile[0] x
+// A.tile[1] elements (cut short at the high edges), taken row of tiles by
+// row of tiles, each tile through all its z-layers before the next, a layer
+// in x-fastest order.  An element's z-neighbours then come one tile-layer
+// apart in the order instead of one whole x-y layer (9216 elements on a 96^3
+// box), close enough for the cache to still hold the face traces they read
+// of each other; with the tile the whole x-y layer, the order is the
+// storage order.
+__device__ __forceinline__ void tiled_coords(const KArgs& A, unsigned lb, long long* ec) {
+  const unsigned n0 = (unsigned)A.N[0], n1 = (unsigned)A.N[1], n2 = (unsigned)A.N[2];
+  const unsigned tx = (unsigned)A.tile[0], ty = (unsigned)A.tile[1];
+  const unsigned rowsz = n0 * ty * n2;  // a full row of tiles (<= E < 2^31)
+  const unsigned r = lb / rowsz;
+  unsigned rem = lb - r * rowsz;
+  const unsigned y0 = r * ty;
+  const unsigned h = min(ty, n1 - y0);
+  const unsigned colsz = tx * h * n2;  // a full tile of this row, all layers
+  const unsigned c = rem / colsz;
+  rem -= c * colsz;
+  const unsigned x0 = c * tx;
+  const unsigned w = min(tx, n0 - x0);
+  const unsigned lay = w * h;
+  const unsigned z = rem / lay;
+  rem -= z * lay;
+  const unsigned yy = rem / w;
+  ec[0] = x0 + (rem - yy * w);
+  ec[1] = y0 + yy;
+  ec[2] = z;
+}
+
+// Launch arguments of the stage pass: the traversal tile of hexahedra.
+template <int DIM>
+inline KArgs stage_args(const KArgs& A) {
+  KArgs B = A;
+  B.tile[0] = (DIM == 3 && DG2P_TILE_3D < A.N[0]) ? DG2P_TILE_3D : A.N[0];
+  B.tile[1] = (DIM == 3 && DG2P_TILE_3D < A.N[1]) ? DG2P_TILE_3D : A.N[1];
+  return B;
 }
 
 // Stores of a pass's outputs (the next state, its face ingredients).  On
@@ -1327,9 +1374,22 @@ __global__ __launch_bounds__(ewg<DIM>(), (min_waves<DIM, VISC>())) void k_stage(
   // its grid coordinates, neighbours and boundary tests are scalar values
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   constexpr int WT = ewg<DIM>();
-  const long long e0 = (blk * (WT / 64) + wv) * EPW + lane / NN;
-  const bool valid = e0 < A.E;
-  const long long e = valid ? e0 : A.E - 1;
+  // element and its multi-index (hexahedra: one per workgroup, in the tiled
+  // traversal order)
+  long long ec[3] = {0, 0, 0};
+  bool valid;
+  long long e;
+  if constexpr (DIM == 3) {
+    static_assert(WT == 64 && EPW == 1, "one hexahedron per workgroup");
+    tiled_coords(A, (unsigned)blk, ec);
+    valid = true;
+    e = ec[0] + A.N[0] * (ec[1] + (long long)A.N[1] * ec[2]);
+  } else {
+    const long long e0 = (blk * (WT / 64) + wv) * EPW + lane / NN;
+    valid = e0 < A.E;
+    e = valid ? e0 : A.E - 1;
+    elem_coords<DIM>(A, e, ec);
+  }
   const int node = lane % NN;
   int ak[3] = {0, 0, 0};
 #pragma unroll
@@ -1352,9 +1412,7 @@ __global__ __launch_bounds__(ewg<DIM>(), (min_waves<DIM, VISC>())) void k_stage(
   if constexpr (MODE == 1) {
     if (io.dt_out && (!io.dt_fixed || io.mon_out)) fused_dt_load<WT>(A, io.rate_in, dt_lds);
   }
-  // element multi-index and face neighbours
-  long long ec[3] = {0, 0, 0};
-  elem_coords<DIM>(A, e, ec);
+  // face neighbours
   long long enb[DIM];
   bool bndk[DIM];
 #pragma unroll

@@ -15,7 +15,8 @@ namespace dg2p {
 namespace {
 
 template <int DIM, bool VISC, bool CSF, int BCK, int PR>
-void stage_mode(int mode, int epi, const KArgs& A, const StageIO& io, hipStream_t s) {
+void stage_mode(int mode, int epi, const KArgs& A0, const StageIO& io, hipStream_t s) {
+  const KArgs A = stage_args<DIM>(A0);
   const dim3 g((unsigned)(8 * A.xcd_chunk)), b(ewg<DIM>());
   if (mode == 0)
     hipLaunchKernelGGL((k_stage<DIM, VISC, CSF, BCK, 0, 0, PR>), g, b, 0, s, A, io);
