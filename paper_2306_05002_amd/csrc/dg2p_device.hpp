@@ -963,20 +963,26 @@ struct GLay {
   }
 };
 // The ingredients of face slot `slot`, node fn of element e: v[0] = a.e_k,
-// v[1 + j] = the traction components.
-template <int DIM, bool VISC>
+// v[1 + j] = the traction components.  NT: a non-temporal load (a slot is
+// read by one element only, the neighbour across its face, so on hexahedra
+// it need not displace the states the neighbours still read from the cache).
+template <int DIM, bool VISC, bool NT = false>
 __device__ __forceinline__ void g_read(const KArgs& A, const double* __restrict__ G, int slot, long long e, int fn,
                                        double* v) {
   using L = GLay<DIM, VISC>;
   if constexpr (L::W == 2) {
 #pragma unroll
     for (int pr = 0; pr < L::P; ++pr) {
-      const dbl2 x = *reinterpret_cast<const dbl2*>(G + L::at(A.E, slot, pr, e, fn));
+      const dbl2* p = reinterpret_cast<const dbl2*>(G + L::at(A.E, slot, pr, e, fn));
+      dbl2 x;
+      if constexpr (NT) x = __builtin_nontemporal_load(p);
+      else x = *p;
       v[2 * pr] = x.x;
       v[2 * pr + 1] = x.y;
     }
   } else {
-    v[0] = G[L::at(A.E, slot, 0, e, fn)];
+    if constexpr (NT) v[0] = __builtin_nontemporal_load(G + L::at(A.E, slot, 0, e, fn));
+    else v[0] = G[L::at(A.E, slot, 0, e, fn)];
   }
 }
 
@@ -1112,7 +1118,7 @@ __device__ __forceinline__ void face_load(const KArgs& A, const double* __restri
 #pragma unroll
   for (int f = 0; f < NF; ++f) qn[f] = Us[(f * A.E + en) * NN + nodee];
   double v[2 * GLay<DIM, VISC>::P];
-  g_read<DIM, VISC>(A, Gin, 2 * kd + 1 - side, en, fn, v);
+  g_read<DIM, VISC, DIM == 3>(A, Gin, 2 * kd + 1 - side, en, fn, v);
   an = v[0];
 #pragma unroll
   for (int j = 0; j < DIM; ++j) tn[j] = VISC ? v[1 + j] : 0.0;
@@ -1534,8 +1540,9 @@ __global__ __launch_bounds__(ewg<DIM>(), (min_waves<DIM, VISC>())) void k_stage(
       }
       const double* src = VISC ? io.Gin + GL::at(A.E, 5 - sg, lane >> 5, eng, lane & 15)
                                : io.Gin + GL::at(A.E, 5 - sg, 0, eng, 2 * part);
+      // non-temporal, as the x- and y-face ingredients (read by this wave only)
       __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src),
-                                       (__attribute__((address_space(3))) void*)&zt_lds[w][2][0], 16, 0, 0);
+                                       (__attribute__((address_space(3))) void*)&zt_lds[w][2][0], 16, 0, 2);
     }
   }
   if constexpr (UN_LDS) {
