@@ -131,7 +131,10 @@ def test_rhs_parity_evolved_state(name, ne, steps):
 
 
 @pytest.mark.parametrize("name,ne", [("drop1d", (37,)), ("drop2d", (7, 5)), ("shock2d", (13, 7)),
-                                     ("adjoint2d", (6, 5)), ("rt3d", (3, 4, 5)), ("bubble2d", (5, 9))])
+                                     ("adjoint2d", (6, 5)), ("rt3d", (3, 4, 5)), ("bubble2d", (5, 9)),
+                                     # hexahedra in more than one 16 x 16 traversal
+                                     # tile per layer, the last cut short in x and y
+                                     ("rt3d", (19, 17, 2))])
 def test_rk_step_and_dt_parity(name, ne):
     cfg, om, prm, U0, mesh, P = gpu_case(name, ne)
     dg = _dg()
