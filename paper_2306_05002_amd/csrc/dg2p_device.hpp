@@ -1476,88 +1476,6 @@ __global__ __launch_bounds__(ewg<DIM>(), (min_waves<DIM, VISC>())) void k_stage(
   closure<DIM>(A, q, pr);
   Grad<DIM, VISC> g;
   gradients<DIM, VISC, PR>(A, q, pr, L, g);
-  // Hexahedra: the z-face neighbour traces and, in the later stages, U^n of
-  // the stage combination go straight from HBM into LDS with gfx950's
-  // global-to-LDS transfers (16 bytes per lane, lane l landing at byte 16 l of
-  // the destination), issued here, once the closure and the gradients have
-  // consumed the element's own loads (after a transfer the compiler's waits
-  // drain every outstanding load), so that they are in flight during the
-  // volume terms and hold no registers.  The kernel waits for them itself
-  // (vmcnt 0) before the z-face pass reads LDS.
-  //   z traces (3 transfers per wave, 1 KB each): the 16 nodes of the layer of
-  //   the neighbour below (its top layer) and above (its bottom layer) are
-  //   contiguous, so lane l = 16 c + 8 s + p fetches doubles 2p, 2p + 1 of
-  //   component c of side s (0 below, 1 above): state fields 0-3, 4-7, and the
-  //   face ingredients (a.e_z, tau.e_z) the neighbour published for that face.
-  //   Slice zt[w][t][32 c + 16 s + face node].
-  //   U^n (4 transfers): lanes 0-31 fetch field 2i, lanes 32-63 field 2i + 1:
-  //   slice un[w][f][node].
-  constexpr bool Z_LDS = DIM == 3;
-  constexpr bool UN_LDS = DIM == 3 && MODE == 2;
-  __shared__ __attribute__((aligned(16))) double zt_lds[Z_LDS ? WT / 64 : 1][Z_LDS ? 3 : 1][Z_LDS ? 128 : 1];
-  __shared__ __attribute__((aligned(16))) double un_lds[UN_LDS ? WT / 64 : 1][UN_LDS ? NF : 1][UN_LDS ? NN : 1];
-  if constexpr (Z_LDS) {
-    const int w = threadIdx.x >> 6;
-    const int sd = (lane >> 3) & 1, part = lane & 7, cc = lane >> 4;
-    // z-neighbour on side sd (uniform in the wave: one element per wave); a
-    // boundary side fetches the element itself (in bounds, unused: ghost)
-    long long en = e;
-    {
-      long long c = ec[2] + (sd ? 1 : -1);
-      bool bnd = false;
-      if (c < 0 || c >= A.N[2]) {
-        if (BCK == 0 || bc_kind(A, 2, sd) == DG2P_BC_PERIODIC)
-          c = (c < 0) ? A.N[2] - 1 : 0;
-        else
-          bnd = true;
-      }
-      if (!bnd) en = e + (c - ec[2]) * ((long long)A.N[0] * A.N[1]);
-    }
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const double* src = Us + ((long long)(4 * t + cc) * A.E + en) * NN + (sd ? 0 : 48) + 2 * part;
-      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src),
-                                       (__attribute__((address_space(3))) void*)&zt_lds[w][t][0], 16, 0, 0);
-    }
-    {
-      // the face ingredients: viscous, lane l = 32 pr + 16 s + node fetches
-      // the pair pr of its node on side s (slice 2 at double 64 pr + 32 s +
-      // 2 node); inviscid, lane l fetches doubles 2p, 2p + 1 of side s as the
-      // traces do (lanes 16-63 repeat lanes 0-15; slice 2 at 16 s + node)
-      using GL = GLay<DIM, VISC>;
-      const int sg = VISC ? ((lane >> 4) & 1) : sd;
-      long long eng = e;
-      {
-        long long c = ec[2] + (sg ? 1 : -1);
-        bool bnd = false;
-        if (c < 0 || c >= A.N[2]) {
-          if (BCK == 0 || bc_kind(A, 2, sg) == DG2P_BC_PERIODIC)
-            c = (c < 0) ? A.N[2] - 1 : 0;
-          else
-            bnd = true;
-        }
-        if (!bnd) eng = e + (c - ec[2]) * ((long long)A.N[0] * A.N[1]);
-      }
-      const double* src = VISC ? io.Gin + GL::at(A.E, 5 - sg, lane >> 5, eng, lane & 15)
-                               : io.Gin + GL::at(A.E, 5 - sg, 0, eng, 2 * part);
-      // non-temporal, as the x- and y-face ingredients (read by this wave only)
-      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src),
-                                       (__attribute__((address_space(3))) void*)&zt_lds[w][2][0], 16, 0, 2);
-    }
-  }
-  if constexpr (UN_LDS) {
-    const int w = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < NF / 2; ++i) {
-      const int f = 2 * i + (lane >> 5);
-      const double* src = io.Un + (f * A.E + e) * NN + 2 * (lane & 31);
-      // non-temporal (cache-policy bit 2): U^n is read once per stage, by
-      // this wave only
-      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src),
-                                       (__attribute__((address_space(3))) void*)&un_lds[w][2 * i][0], 16, 0, 2);
-    }
-  }
-
   double R[NF];
   // volume terms, strong form: R_q = sum_k (1/J_k) D_k (-F_q + s_q a + V_q)_k
 #pragma unroll
@@ -1630,6 +1548,15 @@ __global__ __launch_bounds__(ewg<DIM>(), (min_waves<DIM, VISC>())) void k_stage(
 
   // faces
   const double* __restrict__ Gin = io.Gin;
+  // hexahedra: the z-face neighbour traces, loaded by the z-face lanes before
+  // the x/y faces are evaluated, so that they are in flight meanwhile
+  double qz[NF], anz = 0.0, tz[DIM];
+  if constexpr (DIM == 3) {
+    const int akz = ak[2];
+    if (akz == 0 || akz == 3)
+      face_load<DIM, VISC>(A, Us, Gin, 2, akz == 3, enb[2], node + (3 - 2 * akz) * 16, face_index(node, 2), qz, anz,
+                           tz);
+  }
   if constexpr (DIM >= 2) {
     // The 16 x- and y-face nodes of a quad (4 faces x 4 nodes), or of one
     // z-layer of a hexahedron, are spread over its 16 lanes, one face
@@ -1700,8 +1627,13 @@ __global__ __launch_bounds__(ewg<DIM>(), (min_waves<DIM, VISC>())) void k_stage(
     }
     spread_sym<(DIM > 1 ? 1 : 0), DIM>(A, ak[1], symv, R);
   }
-  // the transfers into LDS issued at entry have landed (uniform point)
-  if constexpr (Z_LDS) __builtin_amdgcn_s_waitcnt(0x0f70);
+  // hexahedra, later stages: U^n of the stage combination, loaded now so that
+  // the loads are in flight during the z-faces
+  [[maybe_unused]] double unr[NF];
+  if constexpr (DIM == 3 && MODE == 2) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) unr[f] = __builtin_nontemporal_load(&io.Un[(f * A.E + e) * NN + node]);
+  }
   {
     // 1D: its faces; 3D: the z-faces (lanes with a_z in {0, 3})
     constexpr int K0 = DIM >= 2 ? 2 : 0;
@@ -1725,22 +1657,12 @@ __global__ __launch_bounds__(ewg<DIM>(), (min_waves<DIM, VISC>())) void k_stage(
           nhk = g.nh[k];
         }
         double qk[NF], ank, tk[DIM];
-        if constexpr (Z_LDS) {
-          const int w = threadIdx.x >> 6;
-          const int slot = 16 * (akk == 3) + (node & 15);
+        if constexpr (DIM == 3) {
 #pragma unroll
-          for (int f = 0; f < NF; ++f) qk[f] = zt_lds[w][f >> 2][32 * (f & 3) + slot];
-          if constexpr (VISC) {
-            // component c of (side, node) at 64 (c / 2) + 32 side + 2 node + c % 2
-            const int b = 32 * (akk == 3) + 2 * (node & 15);
-            ank = zt_lds[w][2][b];
+          for (int f = 0; f < NF; ++f) qk[f] = qz[f];
+          ank = anz;
 #pragma unroll
-            for (int j = 0; j < DIM; ++j) tk[j] = zt_lds[w][2][64 * ((1 + j) >> 1) + b + ((1 + j) & 1)];
-          } else {
-            ank = zt_lds[w][2][slot];
-#pragma unroll
-            for (int j = 0; j < DIM; ++j) tk[j] = 0.0;
-          }
+          for (int j = 0; j < DIM; ++j) tk[j] = tz[j];
         } else {
           face_load<DIM, VISC>(A, Us, Gin, k, akk == 3, enb[k], node + (3 - 2 * akk) * S, face_index(node, k), qk,
                                ank, tk);
@@ -1787,12 +1709,9 @@ __global__ __launch_bounds__(ewg<DIM>(), (min_waves<DIM, VISC>())) void k_stage(
     if constexpr (MODE == 1) {
 #pragma unroll
       for (int f = 0; f < NF; ++f) uo[f] = fma(dt, R[f], q[f]);
-    } else if constexpr (UN_LDS) {
-      // U^n from the wave's LDS slice (its transfer was waited for before
-      // the z-face pass)
-      const int w = threadIdx.x >> 6;
+    } else if constexpr (DIM == 3) {
 #pragma unroll
-      for (int f = 0; f < NF; ++f) uo[f] = fma(A.rk_a, un_lds[w][f][node], A.rk_b * fma(dt, R[f], q[f]));
+      for (int f = 0; f < NF; ++f) uo[f] = fma(A.rk_a, unr[f], A.rk_b * fma(dt, R[f], q[f]));
     } else {
 #pragma unroll
       for (int f = 0; f < NF; ++f) uo[f] = fma(A.rk_a, io.Un[f * fs + o], A.rk_b * fma(dt, R[f], q[f]));
