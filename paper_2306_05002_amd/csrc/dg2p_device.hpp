@@ -568,13 +568,15 @@ __device__ __forceinline__ double nan_min(double a, double b) { return (a < b ||
 
 // ---- lane exchanges of the wave reductions, all on the vector ALU ------------
 // (a few cycles of latency each, where __shfl_xor is an LDS-routed permute).
-// gfx950's v_permlane32_swap(x, y) gives lanes 0-31 x[l + 32] and lanes 32-63
-// y[l - 32] in its second result, and leaves x[l] (lanes 0-31) / y[l]
-// (lanes 32-63) in its first; v_permlane16_swap does the same between the
-// even and odd 16-lane rows (measured).  So with x = the half a lower lane
-// keeps and y = the half an upper lane keeps, first + second is, in every
-// lane, its own half combined with the partner's same half: one step of a
-// reduce-scatter over lane mask 32 (16) without a select.
+// gfx950's v_permlane32_swap(x, y) swaps the upper half-wave of x with the
+// lower half-wave of y: its first result holds x[l] in lanes 0-31 and
+// y[l - 32] in lanes 32-63, its second x[l + 32] in lanes 0-31 and y[l] in
+// lanes 32-63; v_permlane16_swap does the same between the odd 16-lane rows
+// of x and the even rows of y (first: x[l] in even rows, y[l - 16] in odd
+// rows; second: x[l + 16] in even rows, y[l] in odd rows).  So with x = the
+// half a lower lane keeps and y = the half an upper lane keeps, first +
+// second is, in every lane, its own half combined with the partner's same
+// half: one step of a reduce-scatter over lane mask 32 (16) without a select.
 __device__ __forceinline__ unsigned lo32(double v) { return (unsigned)(__double_as_longlong(v) & 0xffffffffull); }
 __device__ __forceinline__ unsigned hi32(double v) { return (unsigned)((unsigned long long)__double_as_longlong(v) >> 32); }
 __device__ __forceinline__ double mk64(unsigned lo, unsigned hi) {
